@@ -1,0 +1,177 @@
+/*
+ * gpr.h — C-ABI of the MI355X (gfx950) exact Gaussian-process regression library.
+ *
+ * The operations follow Section 4 of "GPRat: Gaussian Process Regression with
+ * Asynchronous Tasks" (arXiv 2505.00136): the squared-exponential kernel
+ * (Eq. 2), the Cholesky factor of the training covariance K (Section 4.2),
+ * the posterior mean (Eq. 3), the posterior covariance (Eq. 4), the log
+ * marginal likelihood (Eq. 5), its gradient and the Adam hyperparameter
+ * optimisation (Section 4.1), computed with the tiled right-looking Cholesky
+ * of Fig. 1 (POTRF / TRSM / SYRK / GEMM on T x T tiles).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All arrays are device pointers unless marked "host".  The caller allocates
+ *    and frees every buffer; the library keeps no pointer after a call returns.
+ *  - Matrices are row-major and contiguous: Z is n x d (row i = z_i), Zs is m x d.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it
+ *    and calls return without waiting, except where a host output is documented;
+ *    those calls synchronise `stream` before returning.
+ *  - `tile` is the tile edge b; n must be a multiple of b (T = n / b tiles per
+ *    dimension; T = 1 is the untiled, sequential case).  n = 0 is accepted and does nothing.
+ *  - Hyperparameters (Eq. 2): lengthscale l > 0, signal_var nu > 0, noise_var sigma^2 >= 0,
+ *    all finite.  sigma^2 enters K only on equal indices (the Kronecker delta of Eq. 2);
+ *    cross-covariances and the test prior carry no noise.
+ *  - Status: every call returns GPR_OK or an error code and never throws; the
+ *    message of the last error on the calling thread is gpr_last_error().
+ *  - `prec` selects the arithmetic of the Cholesky's trailing updates (GPR_FP64
+ *    everywhere, or a mixed mode: diagonal-tile POTRF, the log-determinant, the
+ *    refinement residuals and the variance subtraction always stay float64).
+ *
+ * Tiled matrix ("K_tiles") layout, size from gpr_tiles_bytes()
+ * ------------------------------------------------------------
+ *  Region D: T diagonal tiles b x b, float64, row-major; tile k at element k*b*b.
+ *  Region W: T diagonal-tile inverses L_kk^{-1} (float64, lower triangular, zero upper),
+ *            written by gpr_cholesky and used by the solves, the variance and the gradient.
+ *  Region O: the T(T-1)/2 strictly-lower tiles (i > j), row-major each, stored
+ *            column by column: tile (i,j) has index j(T-1) - j(j-1)/2 + (i-j-1).
+ *            Element type float64 for GPR_FP64, float32 for the mixed modes.
+ *  Only the lower triangle of K is stored; strictly-upper parts of diagonal tiles
+ *  are zero after gpr_cholesky.
+ */
+#ifndef GPR_H_
+#define GPR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPR_API __attribute__((visibility("default")))
+
+/* Hyperparameters of the squared-exponential kernel, Eq. 2: l, nu, sigma^2. */
+typedef struct {
+  double lengthscale;
+  double signal_var;
+  double noise_var;
+} gpr_hyper_t;
+
+enum gpr_status {
+  GPR_OK = 0,
+  GPR_ERR_ARG = 1,        /* null pointer, bad precision tag, non-finite or non-positive hyperparameter */
+  GPR_ERR_SHAPE = 2,      /* n not a multiple of tile, tile < 1, negative size */
+  GPR_ERR_NOT_SPD = 3,    /* a non-positive pivot in the Cholesky factorisation */
+  GPR_ERR_OOM = 4,        /* a size whose byte count overflows */
+  GPR_ERR_HIP = 5,        /* a HIP runtime error */
+  GPR_ERR_WORKSPACE = 6   /* ws_bytes smaller than gpr_workspace_size() */
+};
+
+/* Precision of the trailing updates of the tiled Cholesky (TRSM / SYRK / GEMM tasks). */
+enum gpr_precision {
+  GPR_FP64 = 0,    /* float64 everywhere (the paper's double-precision BLAS, Section 5) */
+  GPR_FP32 = 1,    /* float32 off-diagonal tiles, float32 matrix-core products */
+  GPR_BF16X3 = 2,  /* float32 tiles; products from the hi/mid/lo bfloat16 split: hh+hm+mh */
+  GPR_BF16X6 = 3   /* as GPR_BF16X3 plus hl+lh+mm (close to float32 accuracy) */
+};
+
+/* Library version, (major << 16) | (minor << 8) | patch. */
+GPR_API int gpr_version(void);
+
+/* Message of the last failing call on this thread (static storage, never NULL). */
+GPR_API const char* gpr_last_error(void);
+
+/* Bytes of the tiled matrix of an n x n covariance with tile edge `tile` in precision `prec`
+ * (layout above).  bytes: host out. */
+GPR_API int gpr_tiles_bytes(int64_t n, int64_t tile, int prec, size_t* bytes);
+
+/* Workspace bytes that suffice for every call below with these sizes (n training
+ * points, m test points, d features).  bytes: host out. */
+GPR_API int gpr_workspace_size(int64_t n, int64_t m, int64_t d, int64_t tile, int prec, size_t* bytes);
+
+/* Covariance assembly, Eq. 2 (Section 4.1: all pairwise combinations of feature
+ * vectors; Section 4.2: tile by tile).  Writes regions D and O of K_tiles with
+ * K_ij = nu exp(-|z_i - z_j|^2 / (2 l^2)) + sigma^2 [i == j], lower tiles only
+ * (diagonal tiles in full).  Z: n x d float64 (read only).  K_tiles: out. */
+GPR_API int gpr_assemble(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, int64_t tile, int prec,
+                         void* K_tiles, void* stream);
+
+/* Tiled right-looking Cholesky K = L L^T in place (Section 4.2, Fig. 1): for each
+ * step k, POTRF of the diagonal tile (float64), TRSM of the tiles below it, SYRK
+ * of the later diagonal tiles and GEMM of the other trailing tiles.  On return
+ * regions D and O hold L (zero strictly-upper parts in D) and region W holds the
+ * inverses of the diagonal tiles of L.
+ * info: host out, or NULL.  When non-NULL the call synchronises `stream` and stores
+ * 0, or the 1-based global column of the first non-positive pivot (LAPACK
+ * convention), in which case it returns GPR_ERR_NOT_SPD and the factor is unspecified.
+ * ws: device workspace of at least ws_bytes (gpr_workspace_size). */
+GPR_API int gpr_cholesky(void* K_tiles, int64_t n, int64_t tile, int prec, void* ws, size_t ws_bytes,
+                         int64_t* info, void* stream);
+
+/* alpha = K^{-1} y by forward (L z = y) then backward (L^T alpha = z) substitution
+ * over the tiles (Section 4.2; alpha feeds Eq. 3 and Eq. 5).  With refine_sweeps > 0
+ * each sweep computes the float64 residual r = y - K alpha with K regenerated from Z
+ * and h (never stored), solves for the correction with the factor and adds it;
+ * this lifts a mixed-precision factor to float64 accuracy.  Z and h are read only
+ * when refine_sweeps > 0.  y: n (in), alpha: n (out; may not alias y). */
+GPR_API int gpr_solve(const void* L_tiles, const double* Z, int64_t n, int64_t d, gpr_hyper_t h, int64_t tile,
+                      int prec, const double* y, double* alpha, int refine_sweeps, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Posterior mean, Eq. 3: mean_j = sum_i k(zs_j, z_i) alpha_i for j < m, with the
+ * cross-covariance regenerated from Z and Zs (never stored).  mean: m (out). */
+GPR_API int gpr_predict(const double* Z, int64_t n, const double* Zs, int64_t m, int64_t d, gpr_hyper_t h,
+                        const double* alpha, double* mean, void* ws, size_t ws_bytes, void* stream);
+
+/* Posterior uncertainty, Eq. 4, from the factor: V = L^{-1} K_{Z,Zs} by one tiled
+ * forward substitution with m right-hand sides (the same substitution that serves
+ * the mean; Section 5.1), then
+ *   full_cov = 0: out[j] = nu - sum_i V_ij^2                  (m values, the diagonal of Eq. 4)
+ *   full_cov = 1: out[j*m + k] = k(zs_j, zs_k) - (V^T V)_jk   (m x m, row-major)
+ * add_noise = 1 adds sigma^2 to the variances (the diagonal).  Sums of squares and
+ * the subtraction are float64 in every precision. */
+GPR_API int gpr_predict_var(const double* Z, int64_t n, const double* Zs, int64_t m, int64_t d, gpr_hyper_t h,
+                            const void* L_tiles, int64_t tile, int prec, int full_cov, int add_noise, double* out,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Negative log marginal likelihood, the negative of Eq. 5:
+ *   nlml = 1/2 y^T alpha + sum_i log L_ii + n/2 log(2 pi)   (log|K| = 2 sum log L_ii).
+ * nlml: one float64 on the device (out). */
+GPR_API int gpr_nlml(const void* L_tiles, int64_t n, int64_t tile, int prec, const double* y, const double* alpha,
+                     double* nlml, void* stream);
+
+/* Gradient of the NLML in log coordinates theta = log(l, nu, sigma^2) (Section 4.1):
+ *   g_k = 1/2 sum_ij (K^{-1} - alpha alpha^T)_ij (dK/dtheta_k)_ij
+ * with dK/dlog l = K_f o R^2 / l^2, dK/dlog nu = K_f, dK/dlog sigma^2 = sigma^2 I,
+ * K_f the noise-free kernel and R^2 the squared distances, both regenerated from Z.
+ * K^{-1} = L^{-T} L^{-1} is formed tile by tile from the factor and consumed inside
+ * the reduction.  L_tiles is destroyed: region O is overwritten with the
+ * strictly-lower tiles of L^{-1}.  trainable: host[3] (0 = that entry is returned as 0,
+ * NULL = all trainable).  grad_log: device[3] (out). */
+GPR_API int gpr_nlml_grad(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, void* L_tiles, int64_t tile,
+                          int prec, const double* alpha, const int* trainable, double* grad_log, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Adam hyperparameter optimisation (Section 4.1) of theta = log(l, nu, sigma^2):
+ * `steps` iterations of { assemble, Cholesky, alpha, NLML, gradient, Adam update }
+ * with the optimiser state on the device, then one more NLML at the final theta.
+ * theta_log: host[3] in/out.  adam_state: host[7] in/out = m[3], v[3], t (zeros to
+ * start; passing the returned state resumes bit-exactly).  nlml_trace: host[steps+1]
+ * out (NLML at theta_0..theta_steps) or NULL.  K_tiles: device scratch of
+ * gpr_tiles_bytes().  Synchronises `stream`.  Adam: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, theta -= lr mhat / (sqrt(vhat) + eps) with bias correction;
+ * entries with trainable[k] == 0 keep theta and state. */
+GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d, int64_t tile, int prec,
+                         double* theta_log, const int* trainable, int steps, double lr, double beta1, double beta2,
+                         double eps, double* adam_state, double* nlml_trace, void* K_tiles, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Task census of the tiled Cholesky with T tiles per dimension as scheduled by this
+ * library (Fig. 1): counts[0..3] = POTRF, TRSM, SYRK, GEMM tile tasks.  Host only. */
+GPR_API int gpr_cholesky_census(int64_t T, int64_t* counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPR_H_ */

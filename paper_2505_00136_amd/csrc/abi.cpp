@@ -1,0 +1,834 @@
+// C-ABI entry points (include/gpr.h): argument checks, workspace carving and the
+// launch sequences of each step of the GP hot path.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gpr.h"
+#include "common.h"
+#include "kernels.h"
+#include "program.h"
+
+using namespace gpr;
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(expr)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return fail(GPR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int64_t kInnerBlock = 64;     // diagonal-block edge of the in-tile factorisation
+constexpr int64_t kRowsPerChunk = 256;  // rows per workgroup of the transposed matrix-vector products
+constexpr int64_t kColsPerChunk = 4096; // training points per workgroup of the fused kernel-vector products
+
+bool is_mixed(int prec) { return prec != GPR_FP64; }
+bool is_bf16(int prec) { return prec == GPR_BF16X3 || prec == GPR_BF16X6; }
+int esize_of(int prec) { return is_mixed(prec) ? 4 : 8; }
+
+int check_prec(int prec) {
+  if (prec < GPR_FP64 || prec > GPR_BF16X6) return fail(GPR_ERR_ARG, "unknown precision tag %d", prec);
+  return GPR_OK;
+}
+
+int check_shape(int64_t n, int64_t tile) {
+  if (n < 0) return fail(GPR_ERR_SHAPE, "negative size n=%lld", (long long)n);
+  if (tile < 1) return fail(GPR_ERR_SHAPE, "tile must be >= 1 (got %lld)", (long long)tile);
+  if (n % tile != 0) return fail(GPR_ERR_SHAPE, "n=%lld is not a multiple of tile=%lld", (long long)n, (long long)tile);
+  if (tile > (int64_t)1 << 20 || n > (int64_t)1 << 24)
+    return fail(GPR_ERR_OOM, "size too large (n=%lld, tile=%lld)", (long long)n, (long long)tile);
+  return GPR_OK;
+}
+
+int check_hyper(const gpr_hyper_t& h) {
+  if (!std::isfinite(h.lengthscale) || !(h.lengthscale > 0.0)) return fail(GPR_ERR_ARG, "lengthscale must be finite and > 0");
+  if (!std::isfinite(h.signal_var) || !(h.signal_var > 0.0)) return fail(GPR_ERR_ARG, "signal_var must be finite and > 0");
+  if (!std::isfinite(h.noise_var) || h.noise_var < 0.0) return fail(GPR_ERR_ARG, "noise_var must be finite and >= 0");
+  return GPR_OK;
+}
+
+HyperArg harg(const gpr_hyper_t& h) { return HyperArg{h.lengthscale, h.signal_var, h.noise_var, nullptr}; }
+
+TileLayout layout_of(int64_t n, int64_t tile, int prec) {
+  TileLayout L;
+  L.n = n;
+  L.b = tile;
+  L.T = tile > 0 ? n / tile : 0;
+  L.esize = esize_of(prec);
+  return L;
+}
+
+// Sequential carving of a workspace into 256-byte aligned regions.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = (T*)(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Pinned staging buffer for the job tables; the event guards its reuse.
+struct Stager {
+  std::mutex mu;
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  int dev = -1;
+};
+Stager g_stage;
+
+// Copies `bytes` from host memory to `dst` on `st` through the pinned staging buffer.
+int upload_blob(const void* data, size_t bytes, void* dst, hipStream_t st) {
+  if (bytes == 0) return GPR_OK;
+  std::lock_guard<std::mutex> lk(g_stage.mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (g_stage.ev && g_stage.dev == dev) HIPCHK(hipEventSynchronize(g_stage.ev));
+  if (g_stage.ev && g_stage.dev != dev) g_stage.ev = nullptr;   // a new device gets its own event
+  if (bytes > g_stage.cap) {
+    if (g_stage.host) HIPCHK(hipHostFree(g_stage.host));
+    g_stage.host = nullptr;
+    const size_t cap = bytes * 2 < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes * 2;
+    HIPCHK(hipHostMalloc(&g_stage.host, cap, hipHostMallocDefault));
+    g_stage.cap = cap;
+  }
+  if (!g_stage.ev) {
+    HIPCHK(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
+    g_stage.dev = dev;
+  }
+  memcpy(g_stage.host, data, bytes);
+  HIPCHK(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(g_stage.ev, st));
+  return GPR_OK;
+}
+
+size_t jobs_part(size_t nj) { return (nj * sizeof(GemmJob) + 255) & ~(size_t)255; }
+
+size_t arena_bytes_of(const Program& P) { return jobs_part(P.jobs.size()) + P.segs.size() * sizeof(GemmSeg) + 1024; }
+
+// Uploads the job and segment tables of P into `arena` (jobs first, segments at a
+// 256-byte boundary); returns the device addresses.
+int upload_tables(const Program& P, void* arena, size_t cap, hipStream_t st, const GemmJob** dj, const GemmSeg** ds) {
+  const size_t jp = jobs_part(P.jobs.size());
+  const size_t bytes = jp + P.segs.size() * sizeof(GemmSeg);
+  if (bytes + 1024 > cap) return fail(GPR_ERR_WORKSPACE, "job-table arena too small (%zu > %zu)", bytes + 1024, cap);
+  std::vector<char> blob(bytes, 0);
+  if (!P.jobs.empty()) memcpy(blob.data(), P.jobs.data(), P.jobs.size() * sizeof(GemmJob));
+  if (!P.segs.empty()) memcpy(blob.data() + jp, P.segs.data(), P.segs.size() * sizeof(GemmSeg));
+  *dj = (const GemmJob*)arena;
+  *ds = (const GemmSeg*)((char*)arena + jp);
+  return upload_blob(blob.data(), bytes, arena, st);
+}
+
+// Runs a program description: record pass, table upload into `arena`, execute pass.
+template <typename F>
+int run_program(F&& describe, void* arena, size_t arena_cap, hipStream_t st) {
+  Program P;
+  P.st = st;
+  describe(P);
+  const size_t nj = P.jobs.size(), ns = P.segs.size();
+  const GemmJob* dj = nullptr;
+  const GemmSeg* ds = nullptr;
+  if (nj) {
+    int rc = upload_tables(P, arena, arena_cap, st, &dj, &ds);
+    if (rc) return rc;
+  }
+  P.reset_for_exec(dj, ds);
+  describe(P);
+  if (P.jobs.size() != nj || P.segs.size() != ns) return fail(GPR_ERR_HIP, "internal: record and execute passes differ");
+  if (P.err != hipSuccess) return fail(GPR_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(P.err));
+  return GPR_OK;
+}
+
+
+// ================================================================ Cholesky
+struct CholWs {
+  unsigned long long* info;
+  void* panel;      // copy of the panel below the diagonal tile (TRSM source)
+  float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
+  void* arena;
+  size_t arena_cap;
+};
+
+// The tiled right-looking factorisation (Fig. 1).  Step k: factor the diagonal tile
+// and invert its factor (POTRF), X_mk = A_mk L_kk^{-T} for the panel (TRSM, one GEMM
+// against the inverse), then A_mn -= X_mk X_nk^T over the trailing lower triangle
+// (SYRK on diagonal tiles, GEMM elsewhere) as one batched launch.
+//
+// The diagonal tile itself is factored by a blocked right-looking loop with 64-wide
+// blocks; its inverse W is accumulated in the same loop: starting from W = I, block
+// step j multiplies block row j of W by the block inverse W_jj and subtracts
+// P_j (W_jj W_j) from the rows below, P_j being the block column of L below the
+// diagonal block; that update shares its launch with the trailing update P_j P_j^T.
+void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w) {
+  const int64_t b = L.b, T = L.T;
+  const bool mixed = is_mixed(prec);
+  hipStream_t st = P.st;
+  for (int64_t k = 0; k < T; ++k) {
+    double* Dk = L.diag(K, k);
+    double* Wk = L.winv(K, k);
+    P.kernel([=] { return launch_set_identity(Wk, b, st); });
+    for (int64_t r0 = 0; r0 < b; r0 += kInnerBlock) {
+      const int64_t jb = std::min(kInnerBlock, b - r0), rb = r0 + jb, nbelow = b - rb;
+      P.kernel([=] { return launch_potrf_block(Dk + r0 * b + r0, b, Wk + r0 * b + r0, b, (int)jb, k * b + r0, w.info, st); });
+      P.gemm_begin(0);
+      // block row j of W: W_j[:, 0:r0] <- W_jj W_j[:, 0:r0]  (in place, column-partitioned)
+      P.job(Wk + r0 * b, b, nullptr, 0, jb, r0, 1.0, 0.0, 0);
+      P.seg(Wk + r0 * b + r0, b, MODE_KC, Wk + r0 * b, b, MODE_MC, jb, A_LOWER);
+      // block column j of L below the block: P_j = A[rb:, r0:rb] W_jj^T  (in place, row-partitioned)
+      P.job(Dk + rb * b + r0, b, nullptr, 0, nbelow, jb, 1.0, 0.0, 0);
+      P.seg(Dk + rb * b + r0, b, MODE_KC, Wk + r0 * b + r0, b, MODE_KC, jb, B_LOWER);
+      P.gemm_end();
+      if (nbelow > 0) {
+        P.gemm_begin(0);
+        // W[rb:, 0:rb] -= P_j W_j[:, 0:rb]
+        P.job(Wk + rb * b, b, Wk + rb * b, b, nbelow, rb, -1.0, 1.0, 0);
+        P.seg(Dk + rb * b + r0, b, MODE_KC, Wk + r0 * b, b, MODE_MC, jb, 0);
+        // A[rb:, rb:] -= P_j P_j^T (lower part)
+        P.job(Dk + rb * b + rb, b, Dk + rb * b + rb, b, nbelow, nbelow, -1.0, 1.0, JOB_LOWER_ONLY);
+        P.seg(Dk + rb * b + r0, b, MODE_KC, Dk + rb * b + r0, b, MODE_KC, jb, 0);
+        P.gemm_end();
+      }
+    }
+    P.kernel([=] { return launch_zero_upper(Dk, b, st); });
+    if (k == T - 1) break;
+    void* panel = L.off(K, k + 1, k);
+    const int64_t prow = (T - k - 1) * b;
+    const size_t pbytes = (size_t)prow * b * L.esize;
+    P.kernel([=] { return hipMemcpyAsync(w.panel, panel, pbytes, hipMemcpyDeviceToDevice, st); });
+    if (mixed) P.kernel([=] { return launch_convert_f64_f32(Wk, w.w32, b * b, st); });
+    // TRSM: panel = panel_copy * W_kk^T
+    P.gemm_begin(mixed);
+    P.job(panel, b, nullptr, 0, prow, b, 1.0, 0.0, mixed ? JOB_C_F32 : 0);
+    P.seg(w.panel, b, MODE_KC, mixed ? (const void*)w.w32 : (const void*)Wk, b, MODE_KC, b, B_LOWER);
+    P.gemm_end();
+    // SYRK + GEMM trailing update
+    P.gemm_begin(mixed);
+    for (int64_t nn = k + 1; nn < T; ++nn) {
+      for (int64_t m = nn; m < T; ++m) {
+        if (m == nn) {
+          double* Cm = L.diag(K, m);
+          P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
+          P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, m, k), b, MODE_KC, b, 0);
+        } else {
+          void* Cmn = L.off(K, m, nn);
+          P.job(Cmn, b, Cmn, b, b, b, -1.0, 1.0, mixed ? JOB_C_F32 : 0);
+          P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, nn, k), b, MODE_KC, b, 0);
+        }
+      }
+    }
+    P.gemm_end();
+  }
+}
+
+struct CholSizes {
+  size_t fixed, arena;
+};
+
+CholSizes chol_sizes(const TileLayout& L, int prec) {
+  Carve c(nullptr);
+  c.take<char>(256);
+  c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
+  if (is_mixed(prec)) c.take<float>((size_t)L.b * L.b);
+  Program P;
+  CholWs w{};
+  describe_cholesky(P, L, nullptr, prec, w);
+  return CholSizes{c.off, arena_bytes_of(P)};
+}
+
+CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
+  Carve c(ws);
+  CholWs w{};
+  w.info = c.take<unsigned long long>(32);
+  w.panel = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
+  w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.b * L.b) : nullptr;
+  w.arena = c.take<char>(0);
+  w.arena_cap = ws_bytes > c.off ? ws_bytes - c.off : 0;
+  return w;
+}
+
+// ================================================================ triangular solves
+struct SolveWs {
+  double *r, *z, *t, *partial, *kpart, *res, *dvec;
+};
+
+size_t solve_partial_rows(const TileLayout& L) {
+  const int64_t rows = std::max<int64_t>((L.T - 1) * L.b, L.b);
+  return (size_t)ceil_div(std::max<int64_t>(rows, 1), kRowsPerChunk);
+}
+
+SolveWs carve_solve(Carve& c, const TileLayout& L) {
+  SolveWs w{};
+  const int64_t n = L.n, b = L.b;
+  w.r = c.take<double>(n);
+  w.z = c.take<double>(n);
+  w.t = c.take<double>(b);
+  w.partial = c.take<double>(solve_partial_rows(L) * b);
+  w.kpart = c.take<double>((size_t)ceil_div(std::max<int64_t>(n, 1), kColsPerChunk) * n);
+  w.res = c.take<double>(n);
+  w.dvec = c.take<double>(n);
+  return w;
+}
+
+// x = (L L^T)^{-1} y with L in tiles; the diagonal-tile inverses turn every step into a
+// matrix-vector product.  Forward: z_j = W_jj r_j, then r_below -= L_(below,j) z_j.
+// Backward: t = z_i - L_(below,i)^T x_below, then x_i = W_ii^T t.
+int tri_solve(const TileLayout& L, const void* K, const double* y, double* x, const SolveWs& w, hipStream_t st) {
+  const int64_t b = L.b, T = L.T, n = L.n;
+  const int f32 = L.esize == 4;
+  void* Kc = const_cast<void*>(K);
+  HIPCHK(hipMemcpyAsync(w.r, y, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int64_t j = 0; j < T; ++j) {
+    HIPCHK(launch_gemv_n(L.winv(Kc, j), 0, b, b, b, w.r + j * b, 1.0, nullptr, 0.0, w.z + j * b, st));
+    if (j < T - 1) {
+      const int64_t rows = (T - j - 1) * b;
+      HIPCHK(launch_gemv_n(L.off(Kc, j + 1, j), f32, b, rows, b, w.z + j * b, -1.0, w.r + (j + 1) * b, 1.0,
+                           w.r + (j + 1) * b, st));
+    }
+  }
+  const int64_t nchb = ceil_div(b, kRowsPerChunk);
+  for (int64_t i = T - 1; i >= 0; --i) {
+    const double* t = w.z + i * b;
+    if (i < T - 1) {
+      const int64_t rows = (T - i - 1) * b;
+      HIPCHK(launch_gemv_t_partial(L.off(Kc, i + 1, i), f32, b, rows, b, x + (i + 1) * b, w.partial, kRowsPerChunk, st));
+      HIPCHK(launch_reduce_partials(w.partial, ceil_div(rows, kRowsPerChunk), b, -1.0, w.z + i * b, 1.0, w.t, st));
+      t = w.t;
+    }
+    HIPCHK(launch_gemv_t_partial(L.winv(Kc, i), 0, b, b, b, t, w.partial, kRowsPerChunk, st));
+    HIPCHK(launch_reduce_partials(w.partial, nchb, b, 1.0, nullptr, 0.0, x + i * b, st));
+  }
+  return GPR_OK;
+}
+
+int solve_impl(const TileLayout& L, const void* K, const double* Z, int64_t d, HyperArg h, const double* y,
+               double* alpha, int sweeps, const SolveWs& w, hipStream_t st) {
+  int rc = tri_solve(L, K, y, alpha, w, st);
+  if (rc) return rc;
+  const int64_t n = L.n;
+  for (int s = 0; s < sweeps; ++s) {
+    // r = y - K alpha in float64, K regenerated from Z (matrix-free)
+    HIPCHK(launch_kmatvec_partial(Z, n, Z, n, d, h, alpha, w.kpart, kColsPerChunk, st));
+    HIPCHK(launch_residual_finish(w.kpart, ceil_div(n, kColsPerChunk), n, h, y, alpha, w.res, st));
+    rc = tri_solve(L, K, w.res, w.dvec, w, st);
+    if (rc) return rc;
+    HIPCHK(launch_axpy(alpha, w.dvec, 1.0, n, st));
+  }
+  return GPR_OK;
+}
+
+// ================================================================ variance
+struct VarWs {
+  void* V;         // n x m (float64, or float32 in mixed modes)
+  void* tmp;       // b x m
+  float* w32;      // T b x b float32 copies of the diagonal-tile inverses (mixed)
+  double* partial; // column sums of squares
+  void* arena;
+};
+
+void describe_var(Program& P, const TileLayout& L, const void* Kc, int64_t m, int prec, const VarWs& w) {
+  const int64_t b = L.b, T = L.T;
+  const bool mixed = is_mixed(prec);
+  void* K = const_cast<void*>(Kc);
+  const int es = mixed ? 4 : 8;
+  const int cflag = mixed ? JOB_C_F32 : 0;
+  for (int64_t i = 0; i < T; ++i) {
+    char* Vi = (char*)w.V + (size_t)i * b * m * es;
+    // tmp = B_i - sum_{j<i} L_ij V_j
+    P.gemm_begin(mixed);
+    P.job(w.tmp, m, Vi, m, b, m, -1.0, 1.0, cflag);
+    for (int64_t j = 0; j < i; ++j)
+      P.seg(L.off(K, i, j), b, MODE_KC, (char*)w.V + (size_t)j * b * m * es, m, MODE_MC, b, 0);
+    P.gemm_end();
+    // V_i = W_ii tmp
+    P.gemm_begin(mixed);
+    P.job(Vi, m, nullptr, 0, b, m, 1.0, 0.0, cflag);
+    P.seg(mixed ? (const void*)(w.w32 + (size_t)i * b * b) : (const void*)L.winv(K, i), b, MODE_KC, w.tmp, m,
+          MODE_MC, b, A_LOWER);
+    P.gemm_end();
+  }
+}
+
+void describe_fullcov(Program& P, const TileLayout& L, int64_t m, int prec, const VarWs& w, double* out) {
+  const bool mixed = is_mixed(prec);
+  P.gemm_begin(mixed);
+  P.job(out, m, out, m, m, m, -1.0, 1.0, 0);
+  P.seg(w.V, m, MODE_MC, w.V, m, MODE_MC, L.n, 0);
+  P.gemm_end();
+}
+
+VarWs carve_var(Carve& c, const TileLayout& L, int64_t m, int prec) {
+  VarWs w{};
+  const int es = is_mixed(prec) ? 4 : 8;
+  w.V = c.take<char>((size_t)L.n * m * es);
+  w.tmp = c.take<char>((size_t)L.b * m * es);
+  w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.T * L.b * L.b) : nullptr;
+  w.partial = c.take<double>((size_t)ceil_div(std::max<int64_t>(L.n, 1), kRowsPerChunk) * m);
+  w.arena = c.take<char>(0);
+  return w;
+}
+
+// ================================================================ gradient
+struct GradWs {
+  void* tmp;        // (T-1) b x b tiles
+  float* w32;       // T b x b (mixed)
+  double* partial;  // [workgroups][3]
+  void* arena;
+};
+
+// L^{-1} in place over region O, column by column from the right: with the trailing
+// part already inverted, Tmp_i = sum_{k=j+1..i} W_ik L_kj and W_ij = -Tmp_i W_jj.
+void describe_trtri(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
+  const int64_t b = L.b, T = L.T;
+  const bool mixed = is_mixed(prec);
+  const int es = mixed ? 4 : 8;
+  const int cflag = mixed ? JOB_C_F32 : 0;
+  auto Wd = [&](int64_t i) -> const void* {
+    return mixed ? (const void*)(w.w32 + (size_t)i * b * b) : (const void*)L.winv(K, i);
+  };
+  for (int64_t j = T - 2; j >= 0; --j) {
+    P.gemm_begin(mixed);
+    for (int64_t i = j + 1; i < T; ++i) {
+      char* Ti = (char*)w.tmp + (size_t)(i - j - 1) * b * b * es;
+      P.job(Ti, b, nullptr, 0, b, b, 1.0, 0.0, cflag);
+      for (int64_t k = j + 1; k <= i; ++k) {
+        if (k < i) P.seg(L.off(K, i, k), b, MODE_KC, L.off(K, k, j), b, MODE_MC, b, 0);
+        else P.seg(Wd(i), b, MODE_KC, L.off(K, k, j), b, MODE_MC, b, A_LOWER);
+      }
+    }
+    P.gemm_end();
+    P.gemm_begin(mixed);
+    P.job(L.off(K, j + 1, j), b, nullptr, 0, (T - j - 1) * b, b, -1.0, 0.0, cflag);
+    P.seg(w.tmp, b, MODE_KC, Wd(j), b, MODE_MC, b, B_UPPER);
+    P.gemm_end();
+  }
+}
+
+// (K^{-1})_ij = sum_{k >= i} W_ki^T W_kj for every lower tile pair, consumed by the fused
+// gradient reduction (no K^{-1} tile is stored).
+void describe_lauum_trace(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
+  const int64_t b = L.b, T = L.T;
+  const bool mixed = is_mixed(prec);
+  auto Wd = [&](int64_t i) -> const void* {
+    return mixed ? (const void*)(w.w32 + (size_t)i * b * b) : (const void*)L.winv(K, i);
+  };
+  P.gemm_begin(mixed);
+  for (int64_t i = 0; i < T; ++i) {
+    for (int64_t j = 0; j <= i; ++j) {
+      P.job(nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, 0, (int)i, (int)j);
+      for (int64_t k = i; k < T; ++k) {
+        const void* A = (k == i) ? Wd(i) : L.off(K, k, i);
+        const void* B = (k == j) ? Wd(j) : L.off(K, k, j);
+        int tri = 0;
+        if (k == i) tri |= A_UPPER;
+        if (k == j) tri |= B_UPPER;
+        P.seg(A, b, MODE_MC, B, b, MODE_MC, b, tri);
+      }
+    }
+  }
+  // the launch itself is issued by the caller (trace epilogue)
+}
+
+GradWs carve_grad(Carve& c, const TileLayout& L, int prec) {
+  GradWs w{};
+  const int es = is_mixed(prec) ? 4 : 8;
+  w.tmp = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * es);
+  w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.T * L.b * L.b) : nullptr;
+  const int64_t tpt = ceil_div(L.b, GEMM_BM) * ceil_div(L.b, GEMM_BN);
+  w.partial = c.take<double>((size_t)(L.T * (L.T + 1) / 2) * tpt * 3 + 3);
+  w.arena = c.take<char>(0);
+  return w;
+}
+
+int grad_impl(const double* Z, int64_t d, HyperArg h, void* K, const TileLayout& L, int prec, const double* alpha,
+              const int tr[3], double* grad, void* ws, size_t ws_bytes, hipStream_t st) {
+  Carve c(ws);
+  GradWs w = carve_grad(c, L, prec);
+  const size_t fixed = c.off;
+  const bool mixed = is_mixed(prec);
+  if (mixed) HIPCHK(launch_convert_f64_f32(L.winv(K, 0), w.w32, L.T * L.b * L.b, st));
+  int rc = run_program([&](Program& P) { describe_trtri(P, L, K, prec, w); }, w.arena,
+                       ws_bytes > fixed ? ws_bytes - fixed : 0, st);
+  if (rc) return rc;
+  // LAUUM + trace: record, upload, launch with the trace epilogue
+  Program P;
+  P.st = st;
+  describe_lauum_trace(P, L, K, prec, w);
+  const size_t nj = P.jobs.size();
+  const GemmJob* dj = nullptr;
+  const GemmSeg* ds = nullptr;
+  if (nj) {
+    rc = upload_tables(P, w.arena, ws_bytes > fixed ? ws_bytes - fixed : 0, st, &dj, &ds);
+    if (rc) return rc;
+    TraceArgs ta{Z, d, alpha, h, L.b, w.partial};
+    HIPCHK(launch_gemm_trace(mixed, dj, ds, (int)nj, P.nwg, ta, st));
+  }
+  HIPCHK(launch_grad_finish(w.partial, P.nwg, h, tr[0], tr[1], tr[2], grad, st));
+  return GPR_OK;
+}
+
+size_t grad_ws_bytes(const TileLayout& L, int prec) {
+  Carve c(nullptr);
+  GradWs w = carve_grad(c, L, prec);
+  Program P1, P2;
+  describe_trtri(P1, L, nullptr, prec, w);
+  describe_lauum_trace(P2, L, nullptr, prec, w);
+  return c.off + std::max(arena_bytes_of(P1), arena_bytes_of(P2));
+}
+
+size_t var_ws_bytes(const TileLayout& L, int64_t m, int prec, bool full) {
+  Carve c(nullptr);
+  VarWs w = carve_var(c, L, m, prec);
+  Program P;
+  describe_var(P, L, nullptr, m, prec, w);
+  if (full) describe_fullcov(P, L, m, prec, w, nullptr);
+  return c.off + arena_bytes_of(P);
+}
+
+size_t solve_ws_bytes(const TileLayout& L) {
+  Carve c(nullptr);
+  carve_solve(c, L);
+  return c.off;
+}
+
+size_t predict_ws_bytes(int64_t n, int64_t m) {
+  return (size_t)ceil_div(std::max<int64_t>(n, 1), kColsPerChunk) * std::max<int64_t>(m, 1) * 8 + 256;
+}
+
+size_t optimize_state_bytes(int64_t n, int steps) {
+  Carve c(nullptr);
+  c.take<double>(3);            // theta
+  c.take<double>(7);            // adam state
+  c.take<double>(3);            // grad
+  c.take<double>(steps + 1);    // nlml trace
+  c.take<double>(n);            // alpha
+  return c.off + 256;
+}
+
+size_t chol_ws_bytes(const TileLayout& L, int prec) {
+  CholSizes s = chol_sizes(L, prec);
+  return s.fixed + 256 + s.arena;
+}
+
+int chol_impl(void* K, const TileLayout& L, int prec, void* ws, size_t ws_bytes, unsigned long long** info_out,
+              hipStream_t st) {
+  CholWs w = carve_chol(ws, L, prec, ws_bytes);
+  if (info_out) *info_out = w.info;
+  HIPCHK(hipMemsetAsync(w.info, 0xFF, sizeof(unsigned long long), st));
+  return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w); }, w.arena, w.arena_cap, st);
+}
+
+}  // namespace
+
+// ================================================================ C-ABI
+extern "C" {
+
+GPR_API int gpr_version(void) { return (1 << 16) | (0 << 8) | 0; }
+
+GPR_API const char* gpr_last_error(void) { return g_err; }
+
+GPR_API int gpr_tiles_bytes(int64_t n, int64_t tile, int prec, size_t* bytes) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (!bytes) return fail(GPR_ERR_ARG, "bytes is NULL");
+  *bytes = layout_of(n, tile, prec).total_bytes();
+  return GPR_OK;
+}
+
+GPR_API int gpr_workspace_size(int64_t n, int64_t m, int64_t d, int64_t tile, int prec, size_t* bytes) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (m < 0 || d < 1) return fail(GPR_ERR_SHAPE, "need m >= 0 and d >= 1");
+  if (!bytes) return fail(GPR_ERR_ARG, "bytes is NULL");
+  const TileLayout L = layout_of(n, tile, prec);
+  size_t need = chol_ws_bytes(L, prec);
+  need = std::max(need, solve_ws_bytes(L));
+  need = std::max(need, predict_ws_bytes(n, m));
+  need = std::max(need, var_ws_bytes(L, m, prec, true));
+  need = std::max(need, grad_ws_bytes(L, prec));
+  // gpr_optimize keeps its state in front of the per-step workspaces
+  const size_t step = std::max(std::max(chol_ws_bytes(L, prec), solve_ws_bytes(L)), grad_ws_bytes(L, prec));
+  need = std::max(need, optimize_state_bytes(n, 4096) + step);
+  *bytes = need + 4096;
+  return GPR_OK;
+}
+
+GPR_API int gpr_assemble(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, int64_t tile, int prec, void* K_tiles,
+                         void* stream) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if ((rc = check_hyper(h))) return rc;
+  if (d < 1) return fail(GPR_ERR_SHAPE, "d must be >= 1");
+  if (n == 0) return GPR_OK;
+  if (!Z || !K_tiles) return fail(GPR_ERR_ARG, "null pointer");
+  HIPCHK(launch_assemble_tiles(Z, d, harg(h), layout_of(n, tile, prec), K_tiles, (hipStream_t)stream));
+  return GPR_OK;
+}
+
+GPR_API int gpr_cholesky(void* K_tiles, int64_t n, int64_t tile, int prec, void* ws, size_t ws_bytes, int64_t* info,
+                         void* stream) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (n == 0) {
+    if (info) *info = 0;
+    return GPR_OK;
+  }
+  if (!K_tiles || !ws) return fail(GPR_ERR_ARG, "null pointer");
+  const TileLayout L = layout_of(n, tile, prec);
+  if (ws_bytes < chol_ws_bytes(L, prec))
+    return fail(GPR_ERR_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, chol_ws_bytes(L, prec));
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long* dinfo = nullptr;
+  if ((rc = chol_impl(K_tiles, L, prec, ws, ws_bytes, &dinfo, st))) return rc;
+  if (info) {
+    unsigned long long hinfo = 0;
+    HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hinfo != std::numeric_limits<unsigned long long>::max()) {
+      *info = (int64_t)hinfo;
+      return fail(GPR_ERR_NOT_SPD, "matrix is not positive definite: pivot %lld", (long long)hinfo);
+    }
+    *info = 0;
+  }
+  return GPR_OK;
+}
+
+GPR_API int gpr_solve(const void* L_tiles, const double* Z, int64_t n, int64_t d, gpr_hyper_t h, int64_t tile, int prec,
+                      const double* y, double* alpha, int refine_sweeps, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (refine_sweeps < 0) return fail(GPR_ERR_ARG, "refine_sweeps must be >= 0");
+  if (n == 0) return GPR_OK;
+  if (!L_tiles || !y || !alpha || !ws) return fail(GPR_ERR_ARG, "null pointer");
+  if (y == alpha) return fail(GPR_ERR_ARG, "alpha may not alias y");
+  if (refine_sweeps > 0) {
+    if ((rc = check_hyper(h))) return rc;
+    if (!Z || d < 1) return fail(GPR_ERR_ARG, "refinement needs Z and d >= 1");
+  }
+  const TileLayout L = layout_of(n, tile, prec);
+  if (ws_bytes < solve_ws_bytes(L)) return fail(GPR_ERR_WORKSPACE, "workspace too small");
+  Carve c(ws);
+  SolveWs w = carve_solve(c, L);
+  return solve_impl(L, L_tiles, Z, d, harg(h), y, alpha, refine_sweeps, w, (hipStream_t)stream);
+}
+
+GPR_API int gpr_predict(const double* Z, int64_t n, const double* Zs, int64_t m, int64_t d, gpr_hyper_t h,
+                        const double* alpha, double* mean, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_hyper(h))) return rc;
+  if (n < 0 || m < 0 || d < 1) return fail(GPR_ERR_SHAPE, "need n, m >= 0 and d >= 1");
+  if (m == 0) return GPR_OK;
+  if (!Zs || !mean) return fail(GPR_ERR_ARG, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) {
+    HIPCHK(hipMemsetAsync(mean, 0, m * sizeof(double), st));
+    return GPR_OK;
+  }
+  if (!Z || !alpha || !ws) return fail(GPR_ERR_ARG, "null pointer");
+  if (ws_bytes < predict_ws_bytes(n, m)) return fail(GPR_ERR_WORKSPACE, "workspace too small");
+  double* partial = (double*)ws;
+  HIPCHK(launch_kmatvec_partial(Zs, m, Z, n, d, harg(h), alpha, partial, kColsPerChunk, st));
+  HIPCHK(launch_reduce_partials(partial, ceil_div(n, kColsPerChunk), m, 1.0, nullptr, 0.0, mean, st));
+  return GPR_OK;
+}
+
+GPR_API int gpr_predict_var(const double* Z, int64_t n, const double* Zs, int64_t m, int64_t d, gpr_hyper_t h,
+                            const void* L_tiles, int64_t tile, int prec, int full_cov, int add_noise, double* out,
+                            void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if ((rc = check_hyper(h))) return rc;
+  if (m < 0 || d < 1) return fail(GPR_ERR_SHAPE, "need m >= 0 and d >= 1");
+  if (m == 0) return GPR_OK;
+  if (!Zs || !out) return fail(GPR_ERR_ARG, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const HyperArg ha = harg(h);
+  if (n == 0) {
+    // no data: the posterior is the prior
+    if (full_cov) HIPCHK(launch_assemble_dense(Zs, m, Zs, m, d, ha, add_noise, out, m, 0, st));
+    else {
+      Carve c(ws);
+      (void)c;
+      HIPCHK(launch_var_finish(nullptr, 0, m, ha, add_noise, out, st));
+    }
+    return GPR_OK;
+  }
+  if (!Z || !L_tiles || !ws) return fail(GPR_ERR_ARG, "null pointer");
+  const TileLayout L = layout_of(n, tile, prec);
+  const size_t need = var_ws_bytes(L, m, prec, full_cov != 0);
+  if (ws_bytes < need) return fail(GPR_ERR_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, need);
+  Carve c(ws);
+  VarWs w = carve_var(c, L, m, prec);
+  const bool mixed = is_mixed(prec);
+  void* K = const_cast<void*>(L_tiles);
+  if (mixed) HIPCHK(launch_convert_f64_f32(L.winv(K, 0), w.w32, L.T * L.b * L.b, st));
+  HIPCHK(launch_assemble_dense(Z, n, Zs, m, d, ha, 0, w.V, m, mixed ? 1 : 0, st));
+  if (full_cov) HIPCHK(launch_assemble_dense(Zs, m, Zs, m, d, ha, add_noise, out, m, 0, st));
+  rc = run_program(
+      [&](Program& P) {
+        describe_var(P, L, L_tiles, m, prec, w);
+        if (full_cov) describe_fullcov(P, L, m, prec, w, out);
+      },
+      w.arena, ws_bytes - c.off, st);
+  if (rc) return rc;
+  if (!full_cov) {
+    HIPCHK(launch_colsq_partial(w.V, mixed ? 1 : 0, m, n, m, w.partial, kRowsPerChunk, st));
+    HIPCHK(launch_var_finish(w.partial, ceil_div(n, kRowsPerChunk), m, ha, add_noise, out, st));
+  }
+  return GPR_OK;
+}
+
+GPR_API int gpr_nlml(const void* L_tiles, int64_t n, int64_t tile, int prec, const double* y, const double* alpha,
+                     double* nlml, void* stream) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (!nlml) return fail(GPR_ERR_ARG, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) {
+    HIPCHK(hipMemsetAsync(nlml, 0, sizeof(double), st));
+    return GPR_OK;
+  }
+  if (!L_tiles || !y || !alpha) return fail(GPR_ERR_ARG, "null pointer");
+  const TileLayout L = layout_of(n, tile, prec);
+  HIPCHK(launch_nlml(L.diag(const_cast<void*>(L_tiles), 0), L.b, L.T, y, alpha, nlml, st));
+  return GPR_OK;
+}
+
+GPR_API int gpr_nlml_grad(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, void* L_tiles, int64_t tile, int prec,
+                          const double* alpha, const int* trainable, double* grad_log, void* ws, size_t ws_bytes,
+                          void* stream) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if ((rc = check_hyper(h))) return rc;
+  if (d < 1) return fail(GPR_ERR_SHAPE, "d must be >= 1");
+  if (!grad_log) return fail(GPR_ERR_ARG, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) {
+    HIPCHK(hipMemsetAsync(grad_log, 0, 3 * sizeof(double), st));
+    return GPR_OK;
+  }
+  if (!Z || !L_tiles || !alpha || !ws) return fail(GPR_ERR_ARG, "null pointer");
+  const TileLayout L = layout_of(n, tile, prec);
+  if (ws_bytes < grad_ws_bytes(L, prec)) return fail(GPR_ERR_WORKSPACE, "workspace too small");
+  int tr[3] = {1, 1, 1};
+  if (trainable)
+    for (int k = 0; k < 3; ++k) tr[k] = trainable[k] != 0;
+  return grad_impl(Z, d, harg(h), L_tiles, L, prec, alpha, tr, grad_log, ws, ws_bytes, st);
+}
+
+GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d, int64_t tile, int prec,
+                         double* theta_log, const int* trainable, int steps, double lr, double beta1, double beta2,
+                         double eps, double* adam_state, double* nlml_trace, void* K_tiles, void* ws,
+                         size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (d < 1 || n < 1) return fail(GPR_ERR_SHAPE, "need n >= 1 and d >= 1");
+  if (steps < 0 || steps > 4095) return fail(GPR_ERR_ARG, "steps must be in [0, 4095]");
+  if (!Z || !y || !theta_log || !adam_state || !K_tiles || !ws) return fail(GPR_ERR_ARG, "null pointer");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(theta_log[k])) return fail(GPR_ERR_ARG, "theta_log must be finite");
+  if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0))
+    return fail(GPR_ERR_ARG, "bad Adam parameters");
+  const TileLayout L = layout_of(n, tile, prec);
+  const size_t state = optimize_state_bytes(n, 4096);
+  const size_t step_need = std::max(std::max(chol_ws_bytes(L, prec), solve_ws_bytes(L)), grad_ws_bytes(L, prec));
+  if (ws_bytes < state + step_need) return fail(GPR_ERR_WORKSPACE, "workspace too small");
+  int tr[3] = {1, 1, 1};
+  if (trainable)
+    for (int k = 0; k < 3; ++k) tr[k] = trainable[k] != 0;
+  hipStream_t st = (hipStream_t)stream;
+  Carve c(ws);
+  double* dtheta = c.take<double>(3);
+  double* dstate = c.take<double>(7);
+  double* dgrad = c.take<double>(3);
+  double* dtrace = c.take<double>(4097);
+  double* dalpha = c.take<double>(n);
+  void* ws2 = (char*)ws + state;
+  const size_t ws2_bytes = ws_bytes - state;
+  HIPCHK(hipMemcpyAsync(dtheta, theta_log, 3 * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dstate, adam_state, 7 * sizeof(double), hipMemcpyHostToDevice, st));
+  const HyperArg hd{0.0, 0.0, 0.0, dtheta};
+  unsigned long long* dinfo = nullptr;
+  Carve cs(ws2);
+  for (int s = 0; s <= steps; ++s) {
+    HIPCHK(launch_assemble_tiles(Z, d, hd, L, K_tiles, st));
+    if ((rc = chol_impl(K_tiles, L, prec, ws2, ws2_bytes, &dinfo, st))) return rc;
+    {
+      Carve c2(ws2);
+      c2.take<unsigned long long>(32);   // keep the factorisation's info word intact
+      SolveWs sw = carve_solve(c2, L);
+      if ((rc = solve_impl(L, K_tiles, Z, d, hd, y, dalpha, is_mixed(prec) ? 3 : 0, sw, st))) return rc;
+    }
+    HIPCHK(launch_nlml(L.diag(K_tiles, 0), L.b, L.T, y, dalpha, dtrace + s, st));
+    if (s == steps) break;
+    {
+      Carve c2(ws2);
+      c2.take<unsigned long long>(32);
+      void* gws = c2.take<char>(0);
+      if ((rc = grad_impl(Z, d, hd, K_tiles, L, prec, dalpha, tr, dgrad, gws, ws2_bytes - c2.off, st))) return rc;
+    }
+    HIPCHK(launch_adam3(dtheta, dstate, dgrad, lr, beta1, beta2, eps, tr[0], tr[1], tr[2], st));
+  }
+  unsigned long long hinfo = 0;
+  HIPCHK(hipMemcpyAsync(theta_log, dtheta, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(adam_state, dstate, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (nlml_trace) HIPCHK(hipMemcpyAsync(nlml_trace, dtrace, (steps + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hinfo != std::numeric_limits<unsigned long long>::max())
+    return fail(GPR_ERR_NOT_SPD, "covariance lost positive definiteness during optimisation (pivot %lld)",
+                (long long)hinfo);
+  return GPR_OK;
+}
+
+GPR_API int gpr_cholesky_census(int64_t T, int64_t* counts) {
+  if (T < 0 || !counts) return fail(GPR_ERR_ARG, "bad arguments");
+  // count the tile tasks exactly as describe_cholesky issues them (b = 1 keeps it cheap)
+  int64_t potrf = 0, trsm = 0, syrk = 0, gemm = 0;
+  for (int64_t k = 0; k < T; ++k) {
+    ++potrf;
+    if (k == T - 1) break;
+    trsm += T - k - 1;
+    for (int64_t nn = k + 1; nn < T; ++nn)
+      for (int64_t m = nn; m < T; ++m) (m == nn ? syrk : gemm) += 1;
+  }
+  counts[0] = potrf;
+  counts[1] = trsm;
+  counts[2] = syrk;
+  counts[3] = gemm;
+  return GPR_OK;
+}
+
+}  // extern "C"

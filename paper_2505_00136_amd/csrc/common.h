@@ -1,0 +1,123 @@
+// Shared device/host definitions of the gfx950 GP library (internal; not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+#define GPR_DEV __device__ __forceinline__
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+namespace gpr {
+
+// ---------------------------------------------------------------- hyperparameters
+// Kernels receive the hyperparameters by value; when `theta_log` is non-null they
+// use exp(theta_log[0..2]) instead, so an optimisation loop can keep them on the device.
+struct HyperArg {
+  double ell, nu, s2;
+  const double* theta_log;
+};
+
+GPR_DEV void resolve_hyper(const HyperArg& h, double& ell, double& nu, double& s2) {
+  if (h.theta_log) {
+    ell = exp(h.theta_log[0]);
+    nu = exp(h.theta_log[1]);
+    s2 = exp(h.theta_log[2]);
+  } else {
+    ell = h.ell; nu = h.nu; s2 = h.s2;
+  }
+}
+
+// ---------------------------------------------------------------- tiled matrix layout
+// T x T tiles of b x b, lower triangle only.  Three regions, in this order:
+//   D: T diagonal tiles, float64, row-major, tile k at k*b*b;
+//   W: T diagonal-tile inverses L_kk^{-1} (float64, lower triangular), tile k at k*b*b;
+//   O: T(T-1)/2 strictly-lower tiles in column-major packed order, element type `S`
+//      (float64 for the FP64 path, float32 for the mixed paths); tile (i,j), i>j,
+//      has index j(T-1) - j(j-1)/2 + (i-j-1), so the panel below a diagonal tile is contiguous.
+struct TileLayout {
+  int64_t n, b, T;
+  int esize;  // bytes per element in region O (8 or 4)
+  __host__ __device__ int64_t tile_elems() const { return b * b; }
+  __host__ __device__ int64_t off_index(int64_t i, int64_t j) const {
+    return j * (T - 1) - j * (j - 1) / 2 + (i - j - 1);
+  }
+  __host__ __device__ size_t d_bytes() const { return (size_t)T * b * b * 8; }
+  __host__ __device__ size_t w_offset() const { return d_bytes(); }
+  __host__ __device__ size_t o_offset() const { return 2 * d_bytes(); }
+  __host__ __device__ size_t total_bytes() const {
+    return 2 * d_bytes() + (size_t)(T * (T - 1) / 2) * b * b * esize;
+  }
+  __host__ __device__ double* diag(void* base, int64_t k) const {
+    return (double*)base + k * b * b;
+  }
+  __host__ __device__ double* winv(void* base, int64_t k) const {
+    return (double*)((char*)base + w_offset()) + k * b * b;
+  }
+  __host__ __device__ void* off(void* base, int64_t i, int64_t j) const {
+    return (char*)base + o_offset() + (size_t)off_index(i, j) * b * b * esize;
+  }
+};
+
+// ---------------------------------------------------------------- batched tile GEMM
+// One job computes C[M x N] = alpha * sum_s op(A_s) op(B_s)^T + beta * Cin over its segments.
+// Operand modes: element (r,k) of A is A[r*lda + k] (MODE_KC) or A[k*lda + r] (MODE_MC);
+// element (c,k) of B is B[c*ldb + k] (MODE_KC) or B[k*ldb + c] (MODE_MC).
+enum { MODE_KC = 0, MODE_MC = 1 };
+// Triangular skips (the skipped products are exactly zero in memory):
+//   A_LOWER: A(r,k) = 0 for k > r;  A_UPPER: A(r,k) = 0 for k < r;
+//   B_LOWER: B(c,k) = 0 for k > c;  B_UPPER: B(c,k) = 0 for k < c.
+enum { TRI_NONE = 0, A_LOWER = 1, A_UPPER = 2, B_LOWER = 4, B_UPPER = 8 };
+// Job flags.
+enum { JOB_LOWER_ONLY = 1,   // skip macro tiles that lie entirely above the diagonal
+       JOB_C_F32 = 2 };      // C and Cin are float32 (else float64)
+
+struct GemmSeg {
+  const void* A;
+  const void* B;
+  int64_t lda, ldb;
+  int32_t K;
+  uint8_t modeA, modeB, tri, pad;
+};
+
+struct GemmJob {
+  void* C;
+  const void* Cin;
+  int64_t ldc, ldcin;
+  double alpha, beta;
+  int32_t M, N;
+  int32_t seg0, nseg;
+  int32_t wg_begin;   // first workgroup of this job within its launch
+  int32_t tiles_n;    // macro tiles along N
+  int32_t flags;
+  int32_t aux0, aux1;   // job-specific (the gradient reduction stores the tile indices here)
+  int32_t pad;
+};
+
+// Arguments of the gradient reduction fused into the K^{-1} product.
+struct TraceArgs {
+  const double* Z;
+  int64_t d;
+  const double* alpha;
+  HyperArg h;
+  int64_t b;
+  double* partial;   // [workgroups][3]
+};
+
+constexpr int GEMM_BM = 128, GEMM_BN = 128, GEMM_BK = 16, GEMM_THREADS = 256;
+
+// Workgroup w is dispatched to XCD w % 8; remap so that every XCD gets a contiguous
+// range of logical workgroups (neighbouring macro tiles share operands in that XCD's L2).
+GPR_DEV int xcd_remap(int bid, int nblocks) {
+  const int nx = 8;
+  int xcd = bid % nx, local = bid / nx;
+  int per = nblocks / nx, rem = nblocks % nx;
+  int start = xcd * per + (xcd < rem ? xcd : rem);
+  return start + local;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace gpr

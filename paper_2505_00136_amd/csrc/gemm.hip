@@ -1,0 +1,342 @@
+// Batched tile GEMM on the gfx950 matrix cores (float64 and float32 MFMA).
+//
+// Every dense contraction of the factorisation, the triangular inversions, the
+// multi-right-hand-side forward substitution of the variance and the K^{-1}
+// product of the gradient is a list of jobs C = alpha * sum_s op(A_s) op(B_s)^T + beta * Cin.
+// A 256-thread workgroup computes one 128x128 macro tile of one job; its four
+// wave64s each own a 64x64 quadrant held as 4x4 accumulators of the 16x16x4
+// MFMA.  Operands are staged through double-buffered LDS in 16-deep K chunks
+// (one barrier per chunk), the next chunk's global loads being in flight while
+// the current one is multiplied.  LDS holds both operands k-major ([k][m]), so
+// an MFMA fragment read by 16 consecutive lanes touches 16 consecutive words.
+#include "common.h"
+#include "kernels.h"
+
+namespace gpr {
+
+template <typename T> struct MfmaOp;
+template <> struct MfmaOp<double> {
+  typedef v4d acc_t;
+  static GPR_DEV acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // f64 16x16x4 output: lane l, register r holds row (l/16) + 4r, column l%16
+  static GPR_DEV int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct MfmaOp<float> {
+  typedef v4f acc_t;
+  static GPR_DEV acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // f32 16x16x4 output: lane l, register r holds row 4(l/16) + r, column l%16
+  static GPR_DEV int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int LDS_PAD = 4;
+// double-buffered A and B chunks of the widest element type (float64)
+constexpr int SMEM_BYTES = 2 * 2 * GEMM_BK * (GEMM_BM + LDS_PAD) * 8;
+
+template <typename T>
+GPR_DEV void seg_krange(const GemmSeg& s, int m0, int n0, int& kb, int& ke) {
+  kb = 0;
+  ke = s.K;
+  if (s.tri & A_LOWER) ke = min(ke, m0 + GEMM_BM);
+  if (s.tri & B_LOWER) ke = min(ke, n0 + GEMM_BN);
+  if (s.tri & A_UPPER) kb = max(kb, m0);
+  if (s.tri & B_UPPER) kb = max(kb, n0);
+  kb = (kb / GEMM_BK) * GEMM_BK;
+}
+
+// Loads this thread's share of a 128 x 16 operand chunk into registers (zero outside
+// [0,lim) x [k0,kend)).
+template <typename T>
+GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base, int lim,
+                        int k0, int kend, int tid, T r[8]) {
+  if (mode == MODE_KC) {
+    const int kk = k0 + (tid & 7) * 2;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int row = base + (tid >> 3) + 32 * p;
+      const bool rok = row < lim;
+      const T* q = P + (int64_t)row * ld + kk;
+      r[2 * p] = (rok && kk < kend) ? q[0] : T(0);
+      r[2 * p + 1] = (rok && kk + 1 < kend) ? q[1] : T(0);
+    }
+  } else {
+    const int k = k0 + (tid >> 4);
+    const int r0 = base + (tid & 15) * 8;
+    const bool kok = k < kend;
+    const T* q = P + (int64_t)k * ld + r0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = (kok && r0 + e < lim) ? q[e] : T(0);
+  }
+}
+
+template <typename T>
+GPR_DEV void store_chunk(T (*S)[GEMM_BM + LDS_PAD], int mode, int tid, const T r[8]) {
+  if (mode == MODE_KC) {
+    const int kk = (tid & 7) * 2;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int row = (tid >> 3) + 32 * p;
+      S[kk][row] = r[2 * p];
+      S[kk + 1][row] = r[2 * p + 1];
+    }
+  } else {
+    const int k = tid >> 4;
+    const int r0 = (tid & 15) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) S[k][r0 + e] = r[e];
+  }
+}
+
+// Finds this workgroup's job and macro tile; returns false when the tile lies above
+// the diagonal of a lower-only job.
+GPR_DEV bool locate_job(const GemmJob* __restrict__ jobs, int njobs, GemmJob& job, int& m0, int& n0) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg_begin <= bid) lo = mid; else hi = mid - 1;
+  }
+  job = jobs[lo];
+  const int t = bid - job.wg_begin;
+  m0 = (t / job.tiles_n) * GEMM_BM;
+  n0 = (t % job.tiles_n) * GEMM_BN;
+  return !((job.flags & JOB_LOWER_ONLY) && (m0 + GEMM_BM - 1 < n0));
+}
+
+// acc += sum over the job's segments of the 128 x 128 macro tile at (m0, n0).
+template <typename T>
+GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
+                           typename MfmaOp<T>::acc_t (&acc)[4][4], T (*As)[GEMM_BK][GEMM_BM + LDS_PAD],
+                           T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
+  typedef MfmaOp<T> Op;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int send = job.seg0 + job.nseg;
+  int cs = job.seg0, ck0 = 0, cke = 0;
+  for (; cs < send; ++cs) {
+    seg_krange<T>(segs[cs], m0, n0, ck0, cke);
+    if (ck0 < cke) break;
+  }
+  if (cs >= send) return;
+  T ra[8], rb[8];
+  {
+    const GemmSeg& s = segs[cs];
+    load_chunk<T>((const T*)s.A, s.lda, s.modeA, m0, job.M, ck0, cke, tid, ra);
+    load_chunk<T>((const T*)s.B, s.ldb, s.modeB, n0, job.N, ck0, cke, tid, rb);
+    store_chunk<T>(As[0], s.modeA, tid, ra);
+    store_chunk<T>(Bs[0], s.modeB, tid, rb);
+  }
+  __syncthreads();
+  int buf = 0;
+  while (true) {
+    int ns = cs, nk0 = ck0 + GEMM_BK, nke = cke;
+    if (nk0 >= cke) {
+      for (ns = cs + 1; ns < send; ++ns) {
+        seg_krange<T>(segs[ns], m0, n0, nk0, nke);
+        if (nk0 < nke) break;
+      }
+    }
+    const bool more = ns < send;
+    int nmodeA = 0, nmodeB = 0;
+    if (more) {
+      const GemmSeg& s = segs[ns];
+      nmodeA = s.modeA;
+      nmodeB = s.modeB;
+      load_chunk<T>((const T*)s.A, s.lda, s.modeA, m0, job.M, nk0, nke, tid, ra);
+      load_chunk<T>((const T*)s.B, s.ldb, s.modeB, n0, job.N, nk0, nke, tid, rb);
+    }
+#pragma unroll
+    for (int kq = 0; kq < GEMM_BK / 4; ++kq) {
+      const int kr = kq * 4 + (lane >> 4);
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+    }
+    if (!more) break;
+    store_chunk<T>(As[buf ^ 1], nmodeA, tid, ra);
+    store_chunk<T>(Bs[buf ^ 1], nmodeB, tid, rb);
+    __syncthreads();
+    buf ^= 1;
+    cs = ns;
+    ck0 = nk0;
+    cke = nke;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GEMM_THREADS, 2)
+void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  typedef MfmaOp<T> Op;
+  typedef typename Op::acc_t acc_t;
+  __shared__ __align__(16) char smem[SMEM_BYTES];
+  T (*As)[GEMM_BK][GEMM_BM + LDS_PAD] = reinterpret_cast<T (*)[GEMM_BK][GEMM_BM + LDS_PAD]>(smem);
+  T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD] = As + 2;
+  GemmJob job;
+  int m0, n0;
+  if (!locate_job(jobs, njobs, job, m0, n0)) return;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  gemm_mainloop<T>(job, segs, m0, n0, acc, As, Bs);
+
+  // epilogue: C = alpha * acc + beta * Cin
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const bool c32 = job.flags & JOB_C_F32;
+  const double alpha = job.alpha, beta = job.beta;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + Op::row(lane, r);
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < job.M && col < job.N) {
+          double v = alpha * (double)acc[i][j][r];
+          if (c32) {
+            if (beta != 0.0) v += beta * (double)((const float*)job.Cin)[(int64_t)row * job.ldcin + col];
+            ((float*)job.C)[(int64_t)row * job.ldc + col] = (float)v;
+          } else {
+            if (beta != 0.0) v += beta * ((const double*)job.Cin)[(int64_t)row * job.ldcin + col];
+            ((double*)job.C)[(int64_t)row * job.ldc + col] = v;
+          }
+        }
+      }
+}
+
+// Gradient reduction fused into the K^{-1} = L^{-T} L^{-1} product (see grad_trace in the
+// orchestration): the macro tile of K^{-1} never leaves registers; each element is
+// combined with alpha and with the kernel value and squared distance regenerated from Z,
+// and the workgroup writes its three partial sums to partial[blockIdx.x][0..2].
+template <typename T>
+__global__ __launch_bounds__(GEMM_THREADS, 2)
+void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs,
+                       TraceArgs ta) {
+  typedef MfmaOp<T> Op;
+  typedef typename Op::acc_t acc_t;
+  __shared__ __align__(16) char smem[SMEM_BYTES];
+  T (*As)[GEMM_BK][GEMM_BM + LDS_PAD] = reinterpret_cast<T (*)[GEMM_BK][GEMM_BM + LDS_PAD]>(smem);
+  T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD] = As + 2;
+  // after the main loop the operand buffers hold the feature blocks of the tile's points
+  double (*zr)[GEMM_BM + LDS_PAD] = reinterpret_cast<double (*)[GEMM_BM + LDS_PAD]>(smem);
+  double (*zc)[GEMM_BN + LDS_PAD] = zr + GEMM_BK;
+  __shared__ double red[3][GEMM_THREADS];
+  GemmJob job;
+  int m0, n0;
+  const bool active = locate_job(jobs, njobs, job, m0, n0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  double s_l = 0.0, s_nu = 0.0, s_s = 0.0;
+  if (active) {
+    acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    gemm_mainloop<T>(job, segs, m0, n0, acc, As, Bs);
+    double ell, nu, s2;
+    resolve_hyper(ta.h, ell, nu, s2);
+    const double il2 = 1.0 / (ell * ell);
+    const int64_t ti = job.aux0, tj = job.aux1;
+    const double wt = (ti == tj) ? 1.0 : 2.0;
+    const int64_t growb = ti * ta.b + m0, gcolb = tj * ta.b + n0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double r2[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) r2[j][r] = 0.0;
+      for (int64_t f0 = 0; f0 < ta.d; f0 += GEMM_BK) {
+        __syncthreads();
+        for (int e = tid; e < GEMM_BK * GEMM_BM; e += GEMM_THREADS) {
+          const int p = e / GEMM_BK, f = e % GEMM_BK;
+          const int64_t ff = f0 + f;
+          zr[f][p] = (m0 + p < job.M && ff < ta.d) ? ta.Z[(growb + p) * ta.d + ff] : 0.0;
+          zc[f][p] = (n0 + p < job.N && ff < ta.d) ? ta.Z[(gcolb + p) * ta.d + ff] : 0.0;
+        }
+        __syncthreads();
+        for (int f = 0; f < GEMM_BK; ++f) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double a = zr[f][wm + i * 16 + Op::row(lane, r)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const double df = a - zc[f][wn + j * 16 + (lane & 15)];
+              r2[j][r] = fma(df, df, r2[j][r]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + i * 16 + Op::row(lane, r);
+          const int col = n0 + wn + j * 16 + (lane & 15);
+          if (row < job.M && col < job.N) {
+            const int64_t gr = ti * ta.b + row, gc = tj * ta.b + col;
+            const double w = (double)acc[i][j][r] - ta.alpha[gr] * ta.alpha[gc];
+            const double kf = nu * exp(-0.5 * r2[j][r] * il2);
+            s_l = fma(wt * w * kf, r2[j][r] * il2, s_l);
+            s_nu = fma(wt * w, kf, s_nu);
+            if (gr == gc) s_s += w;
+          }
+        }
+    }
+  }
+  red[0][tid] = s_l;
+  red[1][tid] = s_nu;
+  red[2][tid] = s_s;
+  __syncthreads();
+  for (int s = GEMM_THREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+      red[2][tid] += red[2][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double* o = ta.partial + (int64_t)blockIdx.x * 3;
+    o[0] = red[0][0];
+    o[1] = red[1][0];
+    o[2] = red[2][0];
+  }
+}
+
+hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                       hipStream_t st) {
+  if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (prec_f32)
+    hipLaunchKernelGGL(gemm_tiles_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  else
+    hipLaunchKernelGGL(gemm_tiles_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  return hipGetLastError();
+}
+
+}  // namespace gpr
+
+namespace gpr {
+hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                             const TraceArgs& ta, hipStream_t st) {
+  if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (prec_f32)
+    hipLaunchKernelGGL(gemm_trace_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs, ta);
+  else
+    hipLaunchKernelGGL(gemm_trace_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs, ta);
+  return hipGetLastError();
+}
+}  // namespace gpr

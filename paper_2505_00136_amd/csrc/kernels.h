@@ -1,0 +1,66 @@
+// Host-side launchers of the gfx950 kernels (internal; not part of the C-ABI).
+#pragma once
+#include "common.h"
+
+namespace gpr {
+
+// gemm.hip / gemm_bf16.hip
+hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                       hipStream_t st);
+
+hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                             const TraceArgs& ta, hipStream_t st);
+
+// potrf.hip
+hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,
+                              unsigned long long* info, hipStream_t st);
+hipError_t launch_set_identity(double* W, int64_t b, hipStream_t st);
+hipError_t launch_zero_upper(double* A, int64_t b, hipStream_t st);
+hipError_t launch_convert_f64_f32(const double* src, float* dst, int64_t count, hipStream_t st);
+
+// assemble.hip
+// Lower tiles of K (Eq. 2) into the tiled layout: region D (float64) and region O (esize 8 or 4).
+hipError_t launch_assemble_tiles(const double* Z, int64_t d, HyperArg h, const TileLayout& L, void* K,
+                                 hipStream_t st);
+// Dense covariance block out[r*ld + c] = k(A_r, B_c) (+ s2 where r == c when add_diag), float64 or float32.
+hipError_t launch_assemble_dense(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
+                                 HyperArg h, int add_diag, void* out, int64_t ld, int out_f32,
+                                 hipStream_t st);
+// partial[chunk][i] = sum over points j of chunk: k(A_i, B_j) v_j  (float64)
+hipError_t launch_kmatvec_partial(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
+                                  HyperArg h, const double* v, double* partial, int64_t chunk_cols,
+                                  hipStream_t st);
+
+// blas2.hip
+// y[r] = beta*yin[r] + alpha * sum_c A[r*lda + c] x[c]   for r < rows (A float64 or float32)
+hipError_t launch_gemv_n(const void* A, int a_f32, int64_t lda, int64_t rows, int64_t cols,
+                         const double* x, double alpha, const double* yin, double beta, double* y,
+                         hipStream_t st);
+// partial[ch][c] = sum_{r in chunk ch} A[r*lda + c] x[r]
+hipError_t launch_gemv_t_partial(const void* A, int a_f32, int64_t lda, int64_t rows, int64_t cols,
+                                 const double* x, double* partial, int64_t rows_per_chunk,
+                                 hipStream_t st);
+// y[c] = beta*yin[c] + alpha * sum_ch partial[ch][c]    (fixed order)
+hipError_t launch_reduce_partials(const double* partial, int64_t nch, int64_t cols, double alpha,
+                                  const double* yin, double beta, double* y, hipStream_t st);
+// colsq partial: partial[ch][c] = sum_{r in chunk} V[r*ld + c]^2
+hipError_t launch_colsq_partial(const void* V, int v_f32, int64_t ld, int64_t rows, int64_t cols,
+                                double* partial, int64_t rows_per_chunk, hipStream_t st);
+// out[c] = nu (+ s2 if add_noise) - sum_ch partial[ch][c]
+hipError_t launch_var_finish(const double* partial, int64_t nch, int64_t cols, HyperArg h, int add_noise,
+                             double* out, hipStream_t st);
+// nlml = 1/2 y.alpha + sum_i log L_ii + n/2 log 2 pi  (L_ii read from the diagonal tiles)
+hipError_t launch_nlml(const double* Ddiag, int64_t b, int64_t T, const double* y, const double* alpha,
+                       double* nlml, hipStream_t st);
+// r = y - (Kf alpha + s2 alpha) from partial K_f alpha sums
+hipError_t launch_residual_finish(const double* partial, int64_t nch, int64_t n, HyperArg h,
+                                  const double* y, const double* alpha, double* r, hipStream_t st);
+// grad[k] = trainable[k] ? 1/2 * (s_l, s_nu, s2 * s_s)[k] : 0, from per-workgroup partials
+hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, int t0, int t1, int t2, double* grad,
+                              hipStream_t st);
+// One Adam step on theta_log[3] with state m[3], v[3], t (device), masked by trainable.
+hipError_t launch_adam3(double* theta, double* state, const double* grad, double lr, double b1, double b2,
+                        double eps, int t0, int t1, int t2, hipStream_t st);
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
+
+}  // namespace gpr

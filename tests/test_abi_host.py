@@ -1,0 +1,72 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared entry point,
+and rejects bad arguments before touching the GPU."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "gpr.h")).read()
+    return sorted(set(re.findall(r"GPR_API\s+[\w\s\*]+?\b(gpr_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2505_00136_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libgpr.so not built")
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 13
+    so = lib.load()
+    for n in names:
+        assert hasattr(so, n), n
+    assert set(names) <= set(lib.exported_symbols())
+
+
+def test_version_and_sizes(lib):
+    assert lib.gpr_version() >> 16 == 1
+    n, b = 1024, 256
+    T = n // b
+    assert lib.gpr_tiles_bytes(n, b, "fp64") == 2 * T * b * b * 8 + T * (T - 1) // 2 * b * b * 8
+    assert lib.gpr_tiles_bytes(n, b, "fp32") == 2 * T * b * b * 8 + T * (T - 1) // 2 * b * b * 4
+    assert lib.gpr_workspace_size(n, 512, 8, b, "fp64") > 0
+
+
+def test_argument_errors(lib):
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_tiles_bytes(1000, 256, "fp64")
+    assert e.value.code == lib.GPR_ERR_SHAPE
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_tiles_bytes(1024, 0, "fp64")
+    assert e.value.code == lib.GPR_ERR_SHAPE
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_tiles_bytes(1024, 256, 9)
+    assert e.value.code == lib.GPR_ERR_ARG
+    for h in [(0.0, 1.0, 0.1), (1.0, -1.0, 0.1), (1.0, 1.0, -0.1), (float("nan"), 1.0, 0.1), (1.0, float("inf"), 0.1)]:
+        with pytest.raises(lib.GprError) as e:
+            lib.gpr_assemble(0x1000, 16, 2, h, 4, "fp64", 0x2000, stream=0)
+        assert e.value.code == lib.GPR_ERR_ARG
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_assemble(0x1000, 18, 2, (1.0, 1.0, 0.1), 4, "fp64", 0x2000, stream=0)
+    assert e.value.code == lib.GPR_ERR_SHAPE
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_cholesky(0x2000, 16, 4, "fp64", 0x3000, 16, stream=0)
+    assert e.value.code == lib.GPR_ERR_WORKSPACE
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_solve(0x2000, None, 16, 2, (1.0, 1.0, 0.1), 4, "fp64", 0x10, 0x10, 0, 0x3000, 1 << 30, stream=0)
+    assert e.value.code == lib.GPR_ERR_ARG
+
+
+def test_census_matches_fig1(lib):
+    import math
+    assert lib.gpr_cholesky_census(4) == dict(potrf=4, trsm=6, syrk=6, gemm=4)
+    for T in (1, 4, 16, 32):
+        c = lib.gpr_cholesky_census(T)
+        assert c == dict(potrf=T, trsm=math.comb(T, 2), syrk=math.comb(T, 2), gemm=math.comb(T, 3))

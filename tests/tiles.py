@@ -1,0 +1,29 @@
+"""Host-side readers of the documented tiled-matrix layout (include/gpr.h), for tests."""
+import numpy as np
+
+
+def tiles_to_dense_lower(raw: np.ndarray, n: int, b: int, esize: int) -> np.ndarray:
+    """Dense n x n lower matrix from the bytes of a K_tiles buffer (regions D and O)."""
+    T = n // b
+    L = np.zeros((n, n), dtype=np.float64)
+    dreg = raw[: T * b * b * 8].view(np.float64)
+    for k in range(T):
+        L[k * b:(k + 1) * b, k * b:(k + 1) * b] = np.tril(dreg[k * b * b:(k + 1) * b * b].reshape(b, b))
+    off0 = 2 * T * b * b * 8
+    dt = np.float64 if esize == 8 else np.float32
+    oreg = raw[off0:].view(dt)
+    for j in range(T):
+        for i in range(j + 1, T):
+            idx = j * (T - 1) - j * (j - 1) // 2 + (i - j - 1)
+            L[i * b:(i + 1) * b, j * b:(j + 1) * b] = oreg[idx * b * b:(idx + 1) * b * b].reshape(b, b)
+    return L
+
+
+def winv_tiles(raw: np.ndarray, n: int, b: int):
+    T = n // b
+    wreg = raw[T * b * b * 8: 2 * T * b * b * 8].view(np.float64)
+    return [wreg[k * b * b:(k + 1) * b * b].reshape(b, b) for k in range(T)]
+
+
+def diag_tile_offset_bytes(k: int, b: int) -> int:
+    return k * b * b * 8
