@@ -167,6 +167,18 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
                          double eps, double* adam_state, double* nlml_trace, void* K_tiles, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* Profiling hook: while enabled, every trailing-update launch of gpr_cholesky (the
+ * batched SYRK + GEMM of one factorisation step) is bracketed by HIP events on the
+ * call's stream.  Host only; not needed for computing anything. */
+GPR_API int gpr_timing_enable(int on);
+
+/* Waits for the recorded events of one kind of trailing update (kind = 0: float64,
+ * 1: float32, 2: bf16x3, 3: bf16x6) and returns, since the last read of that kind: the
+ * number of launches, their summed duration (ms) and their algorithmic flops (per
+ * step with T' = T-k-1 remaining tiles: T' b^2 (b+1) for the SYRKs plus T'(T'-1) b^3
+ * for the GEMMs).  Resets that kind's record.  All three are host outputs. */
+GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops);
+
 /* Task census of the tiled Cholesky with T tiles per dimension as scheduled by this
  * library (Fig. 1): counts[0..3] = POTRF, TRSM, SYRK, GEMM tile tasks.  Host only. */
 GPR_API int gpr_cholesky_census(int64_t T, int64_t* counts);

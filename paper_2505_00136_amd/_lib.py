@@ -44,6 +44,8 @@ _SIGS = {
     "gpr_optimize": ([_vp, _vp, _i64, _i64, _i64, _int, ctypes.POINTER(_dbl), ctypes.POINTER(_int), _int, _dbl, _dbl,
                       _dbl, _dbl, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _vp, _vp, _sz, _vp], _int),
     "gpr_cholesky_census": ([_i64, ctypes.POINTER(_i64)], _int),
+    "gpr_timing_enable": ([_int], _int),
+    "gpr_timing_read": ([_int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)], _int),
 }
 _EXTRA_SIGS = {}
 
@@ -181,3 +183,18 @@ def gpr_cholesky_census(T):
     c = (_i64 * 4)()
     _check(load().gpr_cholesky_census(T, c))
     return dict(potrf=c[0], trsm=c[1], syrk=c[2], gemm=c[3])
+
+
+def gpr_timing_enable(on: bool):
+    _check(load().gpr_timing_enable(int(on)))
+
+
+TIMING_KINDS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+
+
+def gpr_timing_read(kind="fp64"):
+    """(launches, total_ms, algorithmic_flops) of one kind of trailing-update launch since the last read."""
+    n, ms, fl = _i64(), _dbl(), _dbl()
+    k = TIMING_KINDS[kind] if isinstance(kind, str) else int(kind)
+    _check(load().gpr_timing_read(k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+    return int(n.value), float(ms.value), float(fl.value)

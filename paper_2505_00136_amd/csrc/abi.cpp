@@ -226,7 +226,10 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
     P.seg(w.panel, b, MODE_KC, mixed ? (const void*)w.w32 : (const void*)Wk, b, MODE_KC, b, B_LOWER);
     P.gemm_end();
     // SYRK + GEMM trailing update
-    P.gemm_begin(mixed);
+    {
+      const double tp = (double)(T - k - 1), bd = (double)b;
+      P.gemm_begin(mixed, GEMM_KIND_UPDATE, tp * bd * bd * (bd + 1.0) + tp * (tp - 1.0) * bd * bd * bd);
+    }
     for (int64_t nn = k + 1; nn < T; ++nn) {
       for (int64_t m = nn; m < T; ++m) {
         if (m == nn) {
@@ -810,6 +813,40 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
   if (hinfo != std::numeric_limits<unsigned long long>::max())
     return fail(GPR_ERR_NOT_SPD, "covariance lost positive definiteness during optimisation (pivot %lld)",
                 (long long)hinfo);
+  return GPR_OK;
+}
+
+GPR_API int gpr_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  g_timing.on = on != 0;
+  return GPR_OK;
+}
+
+GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops) {
+  if (!launches || !total_ms || !algo_flops) return fail(GPR_ERR_ARG, "null pointer");
+  if (kind < 0 || kind > 3) return fail(GPR_ERR_ARG, "kind must be 0..3");
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  int64_t cnt = 0;
+  double ms = 0.0, fl = 0.0;
+  std::vector<TimingLog::Rec> keep;
+  for (auto& r : g_timing.recs) {
+    if (r.kind != kind) {
+      keep.push_back(r);
+      continue;
+    }
+    HIPCHK(hipEventSynchronize(r.b));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    fl += r.flops;
+    ++cnt;
+    g_timing.pool.push_back(r.a);
+    g_timing.pool.push_back(r.b);
+  }
+  g_timing.recs.swap(keep);
+  *launches = cnt;
+  *total_ms = ms;
+  *algo_flops = fl;
   return GPR_OK;
 }
 

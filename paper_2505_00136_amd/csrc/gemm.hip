@@ -173,8 +173,7 @@ GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs,
 }
 
 template <typename T>
-__global__ __launch_bounds__(GEMM_THREADS, 2)
-void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
   typedef MfmaOp<T> Op;
   typedef typename Op::acc_t acc_t;
   __shared__ __align__(16) char smem[SMEM_BYTES];
@@ -214,6 +213,21 @@ void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
           }
         }
       }
+}
+
+// General tile products (in-tile factorisation, TRSM, solves, inversion).
+template <typename T>
+__global__ __launch_bounds__(GEMM_THREADS, 2)
+void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  gemm_tiles_body<T>(jobs, segs, njobs);
+}
+
+// The trailing SYRK/GEMM update of a factorisation step (same code, its own symbol so
+// that profiles and timings single it out).
+template <typename T>
+__global__ __launch_bounds__(GEMM_THREADS, 2)
+void gemm_update_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  gemm_tiles_body<T>(jobs, segs, njobs);
 }
 
 // Gradient reduction fused into the K^{-1} = L^{-T} L^{-1} product (see grad_trace in the
@@ -317,13 +331,20 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
   }
 }
 
-hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind,
                        hipStream_t st) {
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
-  if (prec_f32)
-    hipLaunchKernelGGL(gemm_tiles_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
-  else
-    hipLaunchKernelGGL(gemm_tiles_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  if (kind == GEMM_KIND_UPDATE) {
+    if (prec_f32)
+      hipLaunchKernelGGL(gemm_update_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+    else
+      hipLaunchKernelGGL(gemm_update_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  } else {
+    if (prec_f32)
+      hipLaunchKernelGGL(gemm_tiles_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+    else
+      hipLaunchKernelGGL(gemm_tiles_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  }
   return hipGetLastError();
 }
 

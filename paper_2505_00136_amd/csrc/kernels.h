@@ -5,7 +5,8 @@
 namespace gpr {
 
 // gemm.hip / gemm_bf16.hip
-hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_KIND_BF16X6 = 3 };
+hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind,
                        hipStream_t st);
 
 hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,

@@ -8,11 +8,36 @@
 // GEMM launch at its slice of the uploaded tables.
 #pragma once
 #include <functional>
+#include <mutex>
 #include <vector>
 #include "common.h"
 #include "kernels.h"
 
 namespace gpr {
+
+// Optional event timing of the trailing-update launches (a profiling hook of the C-ABI).
+struct TimingLog {
+  std::mutex mu;
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    double flops;
+    int kind;   // 0: float64 update, 1: float32 update, 2: bf16x3 update, 3: bf16x6 update
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+inline TimingLog g_timing;
 
 struct Program {
   bool exec = false;
@@ -23,7 +48,8 @@ struct Program {
   const GemmSeg* dsegs = nullptr;
   hipError_t err = hipSuccess;
   int64_t gemm_flops_wg = 0;   // workgroups launched (statistics)
-  int job0 = 0, nwg = 0, f32 = 0;
+  int job0 = 0, nwg = 0, f32 = 0, kind = 0;
+  double kind_flops = 0.0;
   bool cur_valid = false;
 
   void reset_for_exec(const GemmJob* dj, const GemmSeg* ds) {
@@ -35,10 +61,13 @@ struct Program {
   }
   size_t table_bytes() const { return jobs.size() * sizeof(GemmJob) + segs.size() * sizeof(GemmSeg) + 512; }
 
-  void gemm_begin(int use_f32) {
+  // `algo_flops` is the launch's algorithmic flop count (used by the timing hook).
+  void gemm_begin(int use_f32, int launch_kind = 0, double algo_flops = 0.0) {
     job0 = (int)jobs.size();
     nwg = 0;
     f32 = use_f32;
+    kind = launch_kind;
+    kind_flops = algo_flops;
   }
   // Adds a job C[M x N] = alpha * sum(segments added next) + beta * Cin.
   void job(void* C, int64_t ldc, const void* Cin, int64_t ldcin, int64_t M, int64_t N, double alpha, double beta,
@@ -83,7 +112,24 @@ struct Program {
     const int nj = (int)jobs.size() - job0;
     if (!exec || err != hipSuccess || nj == 0) return;
     gemm_flops_wg += nwg;
-    err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, st);
+    hipEvent_t ea = nullptr, eb = nullptr;
+    bool timed = false;
+    if (kind == GEMM_KIND_UPDATE || kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6) {
+      std::lock_guard<std::mutex> lk(g_timing.mu);
+      if (g_timing.on) {
+        ea = g_timing.get();
+        eb = g_timing.get();
+        timed = ea && eb;
+      }
+    }
+    if (timed) (void)hipEventRecord(ea, st);
+    err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, st);
+    if (timed) {
+      (void)hipEventRecord(eb, st);
+      std::lock_guard<std::mutex> lk(g_timing.mu);
+      const int tk = kind == GEMM_KIND_BF16X3 ? 2 : kind == GEMM_KIND_BF16X6 ? 3 : (f32 ? 1 : 0);
+      g_timing.recs.push_back({ea, eb, kind_flops, tk});
+    }
   }
   // Launches produced by `fn` run only in the execute pass.
   void kernel(const std::function<hipError_t()>& fn) {
