@@ -167,6 +167,13 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
                          double eps, double* adam_state, double* nlml_trace, void* K_tiles, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* The three-way bfloat16 split used by GPR_BF16X3 / GPR_BF16X6 after each panel solve:
+ * hi = rne(x), mid = rne(x - hi), lo = rne(x - hi - mid), each a bfloat16 stored as
+ * uint16 bits (rne = round to nearest, ties to even; the subtractions are exact in
+ * float32, so hi + mid + lo == x for normal x).  x: count float32 (in); hi, mid, lo:
+ * count uint16 each (out). */
+GPR_API int gpr_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, void* stream);
+
 /* Profiling hook: while enabled, every trailing-update launch of gpr_cholesky (the
  * batched SYRK + GEMM of one factorisation step) is bracketed by HIP events on the
  * call's stream.  Host only; not needed for computing anything. */
@@ -176,7 +183,8 @@ GPR_API int gpr_timing_enable(int on);
  * 1: float32, 2: bf16x3, 3: bf16x6) and returns, since the last read of that kind: the
  * number of launches, their summed duration (ms) and their algorithmic flops (per
  * step with T' = T-k-1 remaining tiles: T' b^2 (b+1) for the SYRKs plus T'(T'-1) b^3
- * for the GEMMs).  Resets that kind's record.  All three are host outputs. */
+ * for the GEMMs; the mixed kinds cover the GEMM tiles only, their diagonal-tile SYRK
+ * runs as a separate float64 launch).  Resets that kind's record.  All three are host outputs. */
 GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops);
 
 /* Task census of the tiled Cholesky with T tiles per dimension as scheduled by this

@@ -45,6 +45,7 @@ _SIGS = {
                       _dbl, _dbl, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _vp, _vp, _sz, _vp], _int),
     "gpr_cholesky_census": ([_i64, ctypes.POINTER(_i64)], _int),
     "gpr_timing_enable": ([_int], _int),
+    "gpr_split_bf16x3": ([_vp, _i64, _vp, _vp, _vp, _vp], _int),
     "gpr_timing_read": ([_int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)], _int),
 }
 _EXTRA_SIGS = {}
@@ -187,6 +188,10 @@ def gpr_cholesky_census(T):
 
 def gpr_timing_enable(on: bool):
     _check(load().gpr_timing_enable(int(on)))
+
+
+def gpr_split_bf16x3(x, count, hi, mid, lo, stream=None):
+    _check(load().gpr_split_bf16x3(_ptr(x), count, _ptr(hi), _ptr(mid), _ptr(lo), _stream(stream)))
 
 
 TIMING_KINDS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}

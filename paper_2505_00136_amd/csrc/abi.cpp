@@ -169,6 +169,7 @@ struct CholWs {
   unsigned long long* info;
   void* panel;      // copy of the panel below the diagonal tile (TRSM source)
   float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
+  uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2
   void* arena;
   size_t arena_cap;
 };
@@ -225,22 +226,50 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
     P.job(panel, b, nullptr, 0, prow, b, 1.0, 0.0, mixed ? JOB_C_F32 : 0);
     P.seg(w.panel, b, MODE_KC, mixed ? (const void*)w.w32 : (const void*)Wk, b, MODE_KC, b, B_LOWER);
     P.gemm_end();
-    // SYRK + GEMM trailing update
+    // split-bfloat16 planes of the solved panel
+    const bool split = is_bf16(prec);
+    const int64_t pstride = (T - 1) * b * b;
+    if (split) {
+      uint16_t* pl = w.planes;
+      P.kernel([=] {
+        return launch_split_bf16x3((const float*)panel, prow * b, pl, pl + pstride,
+                                   prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr, st);
+      });
+    }
+    // Trailing update.  float64: SYRK and GEMM tiles in one launch.  Mixed modes: the
+    // SYRK on the float64 diagonal tiles multiplies the float32 panel in float64 (exact
+    // products, so the pivots do not inherit float32 accumulation error); the GEMM tiles
+    // use the mode's products.
+    const double tp = (double)(T - k - 1), bd = (double)b;
+    const double syrk_flops = tp * bd * bd * (bd + 1.0), gemm_flops = tp * (tp - 1.0) * bd * bd * bd;
+    auto opnd = [&](int64_t m) -> const void* {
+      return split ? (const void*)(w.planes + (m - k - 1) * b * b) : (const void*)L.off(K, m, k);
+    };
+    if (mixed) {
+      P.gemm_begin(0, GEMM_KIND_WIDEN);
+      for (int64_t m = k + 1; m < T; ++m) {
+        double* Cm = L.diag(K, m);
+        P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
+        P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, m, k), b, MODE_KC, b, 0);
+      }
+      P.gemm_end();
+    }
     {
-      const double tp = (double)(T - k - 1), bd = (double)b;
-      P.gemm_begin(mixed, GEMM_KIND_UPDATE, tp * bd * bd * (bd + 1.0) + tp * (tp - 1.0) * bd * bd * bd);
+      const int kind = !split ? GEMM_KIND_UPDATE : (prec == GPR_BF16X6 ? GEMM_KIND_BF16X6 : GEMM_KIND_BF16X3);
+      P.gemm_begin(mixed, kind, mixed ? gemm_flops : syrk_flops + gemm_flops);
     }
     for (int64_t nn = k + 1; nn < T; ++nn) {
       for (int64_t m = nn; m < T; ++m) {
         if (m == nn) {
+          if (mixed) continue;
           double* Cm = L.diag(K, m);
           P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
-          P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, m, k), b, MODE_KC, b, 0);
         } else {
           void* Cmn = L.off(K, m, nn);
           P.job(Cmn, b, Cmn, b, b, b, -1.0, 1.0, mixed ? JOB_C_F32 : 0);
-          P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, nn, k), b, MODE_KC, b, 0);
         }
+        P.seg(opnd(m), b, MODE_KC, opnd(nn), b, MODE_KC, b, 0);
+        if (split) P.segs.back().pstrideA = P.segs.back().pstrideB = pstride;
       }
     }
     P.gemm_end();
@@ -256,6 +285,7 @@ CholSizes chol_sizes(const TileLayout& L, int prec) {
   c.take<char>(256);
   c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   if (is_mixed(prec)) c.take<float>((size_t)L.b * L.b);
+  if (is_bf16(prec)) c.take<uint16_t>((size_t)3 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b);
   Program P;
   CholWs w{};
   describe_cholesky(P, L, nullptr, prec, w);
@@ -268,6 +298,7 @@ CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
   w.info = c.take<unsigned long long>(32);
   w.panel = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.b * L.b) : nullptr;
+  w.planes = is_bf16(prec) ? c.take<uint16_t>((size_t)3 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b) : nullptr;
   w.arena = c.take<char>(0);
   w.arena_cap = ws_bytes > c.off ? ws_bytes - c.off : 0;
   return w;
@@ -813,6 +844,14 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
   if (hinfo != std::numeric_limits<unsigned long long>::max())
     return fail(GPR_ERR_NOT_SPD, "covariance lost positive definiteness during optimisation (pivot %lld)",
                 (long long)hinfo);
+  return GPR_OK;
+}
+
+GPR_API int gpr_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, void* stream) {
+  if (count < 0) return fail(GPR_ERR_SHAPE, "negative count");
+  if (count == 0) return GPR_OK;
+  if (!x || !hi || !mid || !lo) return fail(GPR_ERR_ARG, "null pointer");
+  HIPCHK(launch_split_bf16x3(x, count, hi, mid, lo, (hipStream_t)stream));
   return GPR_OK;
 }
 

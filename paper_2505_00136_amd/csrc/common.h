@@ -78,6 +78,7 @@ struct GemmSeg {
   const void* A;
   const void* B;
   int64_t lda, ldb;
+  int64_t pstrideA, pstrideB;   // element stride between the hi/mid/lo bfloat16 planes (split products)
   int32_t K;
   uint8_t modeA, modeB, tri, pad;
 };

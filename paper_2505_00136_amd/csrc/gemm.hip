@@ -51,7 +51,7 @@ GPR_DEV void seg_krange(const GemmSeg& s, int m0, int n0, int& kb, int& ke) {
 // [0,lim) x [k0,kend)).
 template <typename T>
 GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base, int lim,
-                        int k0, int kend, int tid, T r[8]) {
+                        int k0, int kend, int tid, T (&r)[8]) {
   if (mode == MODE_KC) {
     const int kk = k0 + (tid & 7) * 2;
 #pragma unroll
@@ -72,21 +72,21 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
   }
 }
 
-template <typename T>
-GPR_DEV void store_chunk(T (*S)[GEMM_BM + LDS_PAD], int mode, int tid, const T r[8]) {
+template <typename T, typename TL>
+GPR_DEV void store_chunk(T (*S)[GEMM_BM + LDS_PAD], int mode, int tid, const TL (&r)[8]) {
   if (mode == MODE_KC) {
     const int kk = (tid & 7) * 2;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int row = (tid >> 3) + 32 * p;
-      S[kk][row] = r[2 * p];
-      S[kk + 1][row] = r[2 * p + 1];
+      S[kk][row] = (T)r[2 * p];
+      S[kk + 1][row] = (T)r[2 * p + 1];
     }
   } else {
     const int k = tid >> 4;
     const int r0 = (tid & 15) * 8;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) S[k][r0 + e] = r[e];
+    for (int e = 0; e < 8; ++e) S[k][r0 + e] = (T)r[e];
   }
 }
 
@@ -106,8 +106,9 @@ GPR_DEV bool locate_job(const GemmJob* __restrict__ jobs, int njobs, GemmJob& jo
   return !((job.flags & JOB_LOWER_ONLY) && (m0 + GEMM_BM - 1 < n0));
 }
 
-// acc += sum over the job's segments of the 128 x 128 macro tile at (m0, n0).
-template <typename T>
+// acc += sum over the job's segments of the 128 x 128 macro tile at (m0, n0); operands are
+// stored as TL and multiplied as T (float operands may be widened to float64 products).
+template <typename T, typename TL = T>
 GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
                            typename MfmaOp<T>::acc_t (&acc)[4][4], T (*As)[GEMM_BK][GEMM_BM + LDS_PAD],
                            T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
@@ -121,13 +122,13 @@ GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs,
     if (ck0 < cke) break;
   }
   if (cs >= send) return;
-  T ra[8], rb[8];
+  TL ra[8], rb[8];
   {
     const GemmSeg& s = segs[cs];
-    load_chunk<T>((const T*)s.A, s.lda, s.modeA, m0, job.M, ck0, cke, tid, ra);
-    load_chunk<T>((const T*)s.B, s.ldb, s.modeB, n0, job.N, ck0, cke, tid, rb);
-    store_chunk<T>(As[0], s.modeA, tid, ra);
-    store_chunk<T>(Bs[0], s.modeB, tid, rb);
+    load_chunk<TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, ck0, cke, tid, ra);
+    load_chunk<TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, ck0, cke, tid, rb);
+    store_chunk<T, TL>(As[0], s.modeA, tid, ra);
+    store_chunk<T, TL>(Bs[0], s.modeB, tid, rb);
   }
   __syncthreads();
   int buf = 0;
@@ -145,8 +146,8 @@ GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs,
       const GemmSeg& s = segs[ns];
       nmodeA = s.modeA;
       nmodeB = s.modeB;
-      load_chunk<T>((const T*)s.A, s.lda, s.modeA, m0, job.M, nk0, nke, tid, ra);
-      load_chunk<T>((const T*)s.B, s.ldb, s.modeB, n0, job.N, nk0, nke, tid, rb);
+      load_chunk<TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, nk0, nke, tid, ra);
+      load_chunk<TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, nk0, nke, tid, rb);
     }
 #pragma unroll
     for (int kq = 0; kq < GEMM_BK / 4; ++kq) {
@@ -162,8 +163,8 @@ GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs,
         for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
     }
     if (!more) break;
-    store_chunk<T>(As[buf ^ 1], nmodeA, tid, ra);
-    store_chunk<T>(Bs[buf ^ 1], nmodeB, tid, rb);
+    store_chunk<T, TL>(As[buf ^ 1], nmodeA, tid, ra);
+    store_chunk<T, TL>(Bs[buf ^ 1], nmodeB, tid, rb);
     __syncthreads();
     buf ^= 1;
     cs = ns;
@@ -172,7 +173,7 @@ GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs,
   }
 }
 
-template <typename T>
+template <typename T, typename TL = T>
 GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
   typedef MfmaOp<T> Op;
   typedef typename Op::acc_t acc_t;
@@ -187,7 +188,7 @@ GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-  gemm_mainloop<T>(job, segs, m0, n0, acc, As, Bs);
+  gemm_mainloop<T, TL>(job, segs, m0, n0, acc, As, Bs);
 
   // epilogue: C = alpha * acc + beta * Cin
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -220,6 +221,13 @@ template <typename T>
 __global__ __launch_bounds__(GEMM_THREADS, 2)
 void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
   gemm_tiles_body<T>(jobs, segs, njobs);
+}
+
+// float32-stored operands multiplied in float64 (exact products): the diagonal-tile
+// SYRK of the mixed-precision factorisations.
+__global__ __launch_bounds__(GEMM_THREADS, 2)
+void gemm_widen_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  gemm_tiles_body<double, float>(jobs, segs, njobs);
 }
 
 // The trailing SYRK/GEMM update of a factorisation step (same code, its own symbol so
@@ -334,6 +342,12 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind,
                        hipStream_t st) {
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
+    return launch_gemm_bf16(kind == GEMM_KIND_BF16X6 ? 6 : 3, jobs, segs, njobs, nwg, st);
+  if (kind == GEMM_KIND_WIDEN) {
+    hipLaunchKernelGGL(gemm_widen_kernel, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+    return hipGetLastError();
+  }
   if (kind == GEMM_KIND_UPDATE) {
     if (prec_f32)
       hipLaunchKernelGGL(gemm_update_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);

@@ -1,0 +1,195 @@
+// Trailing update with split-BF16 products on the gfx950 matrix cores.
+//
+// After the panel solve, every float32 panel element x is split into three
+// bfloat16 parts hi + mid + lo (round to nearest even at each step; the two
+// residual subtractions are exact in float32).  The update A_mn -= A_mk A_nk^T
+// then sums the bfloat16 products with float32 accumulation on
+// v_mfma_f32_16x16x32_bf16: hh + hm + mh (bf16x3, about 16 significant bits) or
+// additionally hl + lh + mm (bf16x6, close to float32), issuing the small products
+// first within each 32-deep step.  A 256-thread workgroup computes a 128 x 128
+// macro tile; each wave64 owns a 64 x 64 quadrant as 4 x 4 accumulators.  The
+// planes are staged k-contiguous in LDS with an 80-byte row pitch, so one
+// 16-byte fragment read by 16 lanes covers all 64 banks once.
+#include "common.h"
+#include "kernels.h"
+
+namespace gpr {
+
+constexpr int BF_BK = 32;                 // k per chunk (one MFMA k-step)
+constexpr int BF_PITCH = BF_BK + 8;       // bf16 elements per LDS row (80 bytes)
+
+typedef unsigned short bfraw;
+
+GPR_DEV bfraw bf16_rne_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bfraw)((u >> 16) | 0x40);   // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bfraw)(u >> 16);
+}
+GPR_DEV float bf16_to_float(bfraw h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// hi + mid + lo of float32 x
+__global__ void split_bf16x3_kernel(const float* __restrict__ x, int64_t count, bfraw* __restrict__ hi,
+                                   bfraw* __restrict__ mid, bfraw* __restrict__ lo) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = x[i];
+    const bfraw h = bf16_rne_bits(v);
+    const float r1 = v - bf16_to_float(h);
+    const bfraw m = bf16_rne_bits(r1);
+    const float r2 = r1 - bf16_to_float(m);
+    hi[i] = h;
+    mid[i] = m;
+    if (lo) lo[i] = bf16_rne_bits(r2);
+  }
+}
+
+// Loads this thread's share (one row, 16 consecutive k) of a 128 x 32 chunk of one plane.
+GPR_DEV void bf_load(const bfraw* __restrict__ P, int64_t ld, int base, int lim, int k0, int kend, int tid,
+                     uint4& r0, uint4& r1) {
+  const int row = base + (tid >> 1);
+  const int kk = k0 + (tid & 1) * 16;
+  const bfraw* q = P + (int64_t)row * ld + kk;
+  if (row < lim && kk + 16 <= kend && ((((uintptr_t)q) & 15) == 0)) {
+    r0 = *(const uint4*)q;
+    r1 = *(const uint4*)(q + 8);
+  } else {
+    bfraw t[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = (row < lim && kk + e < kend) ? q[e] : (bfraw)0;
+    r0 = make_uint4(t[0] | (t[1] << 16), t[2] | (t[3] << 16), t[4] | (t[5] << 16), t[6] | (t[7] << 16));
+    r1 = make_uint4(t[8] | (t[9] << 16), t[10] | (t[11] << 16), t[12] | (t[13] << 16), t[14] | (t[15] << 16));
+  }
+}
+
+template <int NPLANES>
+GPR_DEV void bf_store(bfraw* S, int tid, const uint4 (&r)[NPLANES][2]) {
+  const int row = tid >> 1, kk = (tid & 1) * 16;
+#pragma unroll
+  for (int p = 0; p < NPLANES; ++p) {
+    uint4* d = (uint4*)(S + (p * GEMM_BM + row) * BF_PITCH + kk);
+    d[0] = r[p][0];
+    d[1] = r[p][1];
+  }
+}
+
+GPR_DEV v8bf frag(const bfraw* S, int plane, int row, int koff) {
+  const uint4 v = *(const uint4*)(S + (plane * GEMM_BM + row) * BF_PITCH + koff);
+  return __builtin_bit_cast(v8bf, v);
+}
+
+GPR_DEV v4f mma_bf16(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+// NPROD = 3 (hh, hm, mh) or 6 (+ hl, lh, mm).  Operands are MODE_KC with no triangular skips.
+template <int NPROD>
+__global__ __launch_bounds__(GEMM_THREADS, 2)
+void gemm_bf16x_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  constexpr int NP = NPROD == 6 ? 3 : 2;   // planes needed
+  __shared__ __align__(16) bfraw As[NP * GEMM_BM * BF_PITCH];
+  __shared__ __align__(16) bfraw Bs[NP * GEMM_BN * BF_PITCH];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg_begin <= bid) lo = mid; else hi = mid - 1;
+  }
+  const GemmJob job = jobs[lo];
+  const int t = bid - job.wg_begin;
+  const int m0 = (t / job.tiles_n) * GEMM_BM;
+  const int n0 = (t % job.tiles_n) * GEMM_BN;
+  if ((job.flags & JOB_LOWER_ONLY) && (m0 + GEMM_BM - 1 < n0)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int s = job.seg0; s < job.seg0 + job.nseg; ++s) {
+    const GemmSeg sg = segs[s];
+    const bfraw* A = (const bfraw*)sg.A;
+    const bfraw* B = (const bfraw*)sg.B;
+    for (int k0 = 0; k0 < sg.K; k0 += BF_BK) {
+      uint4 ra[NP][2], rb[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        bf_load(A + p * sg.pstrideA, sg.lda, m0, job.M, k0, sg.K, tid, ra[p][0], ra[p][1]);
+        bf_load(B + p * sg.pstrideB, sg.ldb, n0, job.N, k0, sg.K, tid, rb[p][0], rb[p][1]);
+      }
+      __syncthreads();   // previous chunk fully consumed
+      bf_store<NP>(As, tid, ra);
+      bf_store<NP>(Bs, tid, rb);
+      __syncthreads();
+      const int koff = (lane >> 4) * 8;
+      v8bf a[4][NP];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) a[i][p] = frag(As, p, wm + i * 16 + (lane & 15), koff);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v8bf b[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) b[p] = frag(Bs, p, wn + j * 16 + (lane & 15), koff);
+        // small products first: (mm, lh, hl), then (mh, hm), then hh
+        if (NPROD == 6) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf16(a[i][1], b[1], acc[i][j]);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf16(a[i][2 % NP], b[0], acc[i][j]);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf16(a[i][0], b[2 % NP], acc[i][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf16(a[i][1], b[0], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf16(a[i][0], b[1], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf16(a[i][0], b[0], acc[i][j]);
+      }
+    }
+  }
+
+  const bool c32 = job.flags & JOB_C_F32;
+  const double alpha = job.alpha, beta = job.beta;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < job.M && col < job.N) {
+          double v = alpha * (double)acc[i][j][r];
+          if (c32) {
+            if (beta != 0.0) v += beta * (double)((const float*)job.Cin)[(int64_t)row * job.ldcin + col];
+            ((float*)job.C)[(int64_t)row * job.ldc + col] = (float)v;
+          } else {
+            if (beta != 0.0) v += beta * ((const double*)job.Cin)[(int64_t)row * job.ldcin + col];
+            ((double*)job.C)[(int64_t)row * job.ldc + col] = v;
+          }
+        }
+      }
+}
+
+hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, hipStream_t st) {
+  if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (nprod == 6)
+    hipLaunchKernelGGL(gemm_bf16x_kernel<6>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  else
+    hipLaunchKernelGGL(gemm_bf16x_kernel<3>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  int64_t g = (count + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(split_bf16x3_kernel, dim3((unsigned)g), dim3(256), 0, st, x, count, (bfraw*)hi, (bfraw*)mid,
+                     (bfraw*)lo);
+  return hipGetLastError();
+}
+
+}  // namespace gpr

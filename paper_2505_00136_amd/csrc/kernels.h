@@ -5,12 +5,19 @@
 namespace gpr {
 
 // gemm.hip / gemm_bf16.hip
-enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_KIND_BF16X6 = 3 };
+// GENERIC/UPDATE: operands and products in the launch precision; WIDEN: float32 operands,
+// float64 products; BF16X3/X6: split-bfloat16 products of bfloat16 planes.
+enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_KIND_BF16X6 = 3, GEMM_KIND_WIDEN = 4 };
 hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind,
                        hipStream_t st);
 
 hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
                              const TraceArgs& ta, hipStream_t st);
+
+// gemm_bf16.hip: trailing update from split-bfloat16 planes (nprod 3 or 6); KC operands only
+hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, hipStream_t st);
+// hi/mid/lo bfloat16 parts (round to nearest even) of float32 x; lo may be null
+hipError_t launch_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, hipStream_t st);
 
 // potrf.hip
 hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,

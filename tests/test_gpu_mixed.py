@@ -1,0 +1,96 @@
+"""GPU parity of the mixed-precision paths against the FP64 oracle.
+
+Bounds (stated, derived from the arithmetic):
+* the float32 / bf16x6 factor has a backward error of order n u32 ||K|| (u32 = 6e-8);
+  after three float64 refinement sweeps alpha and the mean are limited by
+  (kappa u32)^4 plus float64 rounding, so they must match the oracle to 1e-6 (the
+  target for mean and NLML) and in practice reach ~1e-10;
+* the NLML takes log|K| from the mixed factor: its relative error is bounded by
+  n u32 kappa-weighted terms / |NLML|, required here <= 1e-6;
+* the variance uses the mixed factor without refinement (float64 sums and subtraction),
+  so its error is of order kappa u32: bound 1e-4 relative (stated bound for the variance);
+* bf16x3 keeps about 16 significant bits per product, so its bounds are 1e-4 (NLML)
+  and 1e-3 (variance), and alpha converges only while kappa 2^-16 < 1.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import Hyper
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from tests.tiles import tiles_to_dense_lower  # noqa: E402
+from tests.test_gpu_parity import _gpu_fit, _gpu_predict, _rel, lib  # noqa: E402,F401
+
+
+def test_split_bf16x3_bit_exact(lib):
+    rng = np.random.default_rng(5)
+    x = (rng.normal(size=100003) * 10.0 ** rng.uniform(-6, 6, size=100003)).astype(np.float32)
+    x[:5] = [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -(1.0 + 2 ** -8), 0.0, -0.0]
+    dev = "cuda:0"
+    xt = torch.tensor(x, device=dev)
+    parts = [torch.empty(x.size, dtype=torch.int16, device=dev) for _ in range(3)]
+    lib.gpr_split_bf16x3(xt, x.size, *parts)
+    torch.cuda.synchronize()
+    ref = oracle.split_bf16x3(x)
+    for got, want in zip(parts, ref):
+        bits = (want.view(np.uint32) >> 16).astype(np.uint16)
+        np.testing.assert_array_equal(got.cpu().numpy().view(np.uint16), bits)
+
+
+@pytest.fixture(scope="module")
+def dense_case():
+    # a dense, moderately conditioned K (lengthscale sqrt(D)), several tiles and a ragged tile edge
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=1000, n_test=300, D=16, seed=11))
+    h = Hyper(math.sqrt(16), 1.0, 0.01)
+    L, a, f = oracle.fit(ds.Z, ds.y, h)
+    return ds, h, L, a, f
+
+
+@pytest.mark.parametrize("prec,tol_nlml,tol_var", [("fp32", 1e-6, 1e-4), ("bf16x6", 1e-6, 1e-4),
+                                                   ("bf16x3", 1e-4, 1e-3)])
+def test_mixed_factor_mean_var_nlml(lib, dense_case, prec, tol_nlml, tol_var):
+    ds, h, L, a, f = dense_case
+    tile = 200
+    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, prec=prec, sweeps=3, m=300)
+    raw = g["K"].cpu().numpy()
+    Lg = tiles_to_dense_lower(raw, 1000, tile, 4)
+    ferr = np.max(np.abs(Lg - L)) / np.max(np.abs(L))
+    assert ferr < (1e-4 if prec != "bf16x3" else 1e-2)
+    assert abs(g["nlml"] - f) / abs(f) < tol_nlml
+    mean, var = _gpu_predict(lib, g, ds.Zs, h)
+    mo = oracle.predict_mean(ds.Z, ds.Zs, h, a)
+    if prec != "bf16x3":
+        assert _rel(g["alpha"].cpu().numpy(), a) < 1e-6
+        assert _rel(mean, mo) < 1e-6
+    vo = oracle.predict_var(ds.Z, ds.Zs, h, L)
+    assert _rel(var, vo) < tol_var
+
+
+def test_refinement_residual_decreases(lib, dense_case):
+    ds, h, L, a, f = dense_case
+    K = oracle.train_cov(ds.Z, h)
+    errs = []
+    for sweeps in range(4):
+        g = _gpu_fit(lib, ds.Z, ds.y, h, 250, prec="fp32", sweeps=sweeps)
+        al = g["alpha"].cpu().numpy()
+        errs.append(np.linalg.norm(K @ al - ds.y) / np.linalg.norm(ds.y))
+    assert all(e1 <= e0 * 1.0001 for e0, e1 in zip(errs[:-1], errs[1:]))
+    assert errs[-1] < 1e-9 < errs[0]
+
+
+def test_mixed_gradient_and_full_cov(lib, dense_case):
+    ds, h, L, a, f = dense_case
+    go = oracle.nlml_grad(ds.Z, h, L, a)
+    g = _gpu_fit(lib, ds.Z, ds.y, h, 200, prec="fp32", sweeps=3, m=100)
+    _, S = _gpu_predict(lib, g, ds.Zs[:100], h, full_cov=True)
+    So = oracle.predict_var(ds.Z, ds.Zs[:100], h, L, full_cov=True)
+    assert np.linalg.norm(S - So) / np.linalg.norm(So) < 1e-4
+    grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    lib.gpr_nlml_grad(g["Z"], g["n"], g["d"], h, g["K"], 200, "fp32", g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
+    np.testing.assert_allclose(grad.cpu().numpy(), go, rtol=1e-3, atol=1e-3 * np.max(np.abs(go)))
