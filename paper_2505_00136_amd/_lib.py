@@ -46,6 +46,14 @@ _SIGS = {
     "gpr_cholesky_census": ([_i64, ctypes.POINTER(_i64)], _int),
     "gpr_timing_enable": ([_int], _int),
     "gpr_split_bf16x3": ([_vp, _i64, _vp, _vp, _vp, _vp], _int),
+    "gpr_stats_workspace": ([_i64, ctypes.POINTER(_sz)], _int),
+    "gpr_summary_stats": ([_vp, _vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _sz, _vp], _int),
+    "gpr_mlp_nparams": ([], _int),
+    "gpr_mlp_workspace": ([_i64, ctypes.POINTER(_sz)], _int),
+    "gpr_mlp_forward": ([_vp, _vp, _i64, _vp, _vp, _sz, _vp], _int),
+    "gpr_mlp_loss_grad": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp], _int),
+    "gpr_mlp_train_step": ([_vp, _vp, _vp, _int, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, _vp, _vp, _sz, _vp], _int),
     "gpr_timing_read": ([_int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)], _int),
 }
 _EXTRA_SIGS = {}
@@ -192,6 +200,42 @@ def gpr_timing_enable(on: bool):
 
 def gpr_split_bf16x3(x, count, hi, mid, lo, stream=None):
     _check(load().gpr_split_bf16x3(_ptr(x), count, _ptr(hi), _ptr(mid), _ptr(lo), _stream(stream)))
+
+
+def gpr_stats_workspace(nsub) -> int:
+    out = _sz()
+    _check(load().gpr_stats_workspace(nsub, ctypes.byref(out)))
+    return out.value
+
+
+def gpr_summary_stats(Z_raw, Z_std, y_raw, n, d, sub_idx, nsub, stats64, stats32, ws, ws_bytes, stream=None):
+    _check(load().gpr_summary_stats(_ptr(Z_raw), _ptr(Z_std), _ptr(y_raw), n, d, _ptr(sub_idx), nsub, _ptr(stats64),
+                                    _ptr(stats32), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def gpr_mlp_nparams() -> int:
+    return load().gpr_mlp_nparams()
+
+
+def gpr_mlp_workspace(batch) -> int:
+    out = _sz()
+    _check(load().gpr_mlp_workspace(batch, ctypes.byref(out)))
+    return out.value
+
+
+def gpr_mlp_forward(params, X, batch, out, ws, ws_bytes, stream=None):
+    _check(load().gpr_mlp_forward(_ptr(params), _ptr(X), batch, _ptr(out), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def gpr_mlp_loss_grad(params, X, Y, batch, loss, grad, ws, ws_bytes, stream=None):
+    _check(load().gpr_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(Y), batch, _ptr(loss), _ptr(grad), _ptr(ws),
+                                    ws_bytes, _stream(stream)))
+
+
+def gpr_mlp_train_step(params, adam_m, adam_v, t, X, Y, batch, lr, beta1, beta2, eps, loss, ws, ws_bytes,
+                       stream=None):
+    _check(load().gpr_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), t, _ptr(X), _ptr(Y), batch, lr, beta1,
+                                     beta2, eps, _ptr(loss), _ptr(ws), ws_bytes, _stream(stream)))
 
 
 TIMING_KINDS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}

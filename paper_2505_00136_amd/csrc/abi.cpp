@@ -170,6 +170,7 @@ struct CholWs {
   void* panel;      // copy of the panel below the diagonal tile (TRSM source)
   float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
   uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2
+
   void* arena;
   size_t arena_cap;
 };
@@ -572,6 +573,7 @@ int chol_impl(void* K, const TileLayout& L, int prec, void* ws, size_t ws_bytes,
   CholWs w = carve_chol(ws, L, prec, ws_bytes);
   if (info_out) *info_out = w.info;
   HIPCHK(hipMemsetAsync(w.info, 0xFF, sizeof(unsigned long long), st));
+
   return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w); }, w.arena, w.arena_cap, st);
 }
 
@@ -642,12 +644,12 @@ GPR_API int gpr_cholesky(void* K_tiles, int64_t n, int64_t tile, int prec, void*
   unsigned long long* dinfo = nullptr;
   if ((rc = chol_impl(K_tiles, L, prec, ws, ws_bytes, &dinfo, st))) return rc;
   if (info) {
-    unsigned long long hinfo = 0;
-    HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+    unsigned long long hinfo[1] = {0};
+    HIPCHK(hipMemcpyAsync(hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (hinfo != std::numeric_limits<unsigned long long>::max()) {
-      *info = (int64_t)hinfo;
-      return fail(GPR_ERR_NOT_SPD, "matrix is not positive definite: pivot %lld", (long long)hinfo);
+    if (hinfo[0] != std::numeric_limits<unsigned long long>::max()) {
+      *info = (int64_t)hinfo[0];
+      return fail(GPR_ERR_NOT_SPD, "matrix is not positive definite: pivot %lld", (long long)hinfo[0]);
     }
     *info = 0;
   }
@@ -852,6 +854,74 @@ GPR_API int gpr_split_bf16x3(const float* x, int64_t count, void* hi, void* mid,
   if (count == 0) return GPR_OK;
   if (!x || !hi || !mid || !lo) return fail(GPR_ERR_ARG, "null pointer");
   HIPCHK(launch_split_bf16x3(x, count, hi, mid, lo, (hipStream_t)stream));
+  return GPR_OK;
+}
+
+GPR_API int gpr_stats_workspace(int64_t nsub, size_t* bytes) {
+  if (nsub < 2 || nsub > 4096 || !bytes) return fail(GPR_ERR_ARG, "need 2 <= nsub <= 4096 and bytes");
+  *bytes = (size_t)stats_sort_len(nsub) * sizeof(double) + 256;
+  return GPR_OK;
+}
+
+GPR_API int gpr_summary_stats(const double* Z_raw, const double* Z_std, const double* y_raw, int64_t n, int64_t d,
+                              const int64_t* sub_idx, int64_t nsub, double* stats64, float* stats32, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (n < 1 || d < 1 || d > 256) return fail(GPR_ERR_SHAPE, "need n >= 1 and 1 <= d <= 256");
+  if (nsub < 2 || nsub > 4096 || nsub > n) return fail(GPR_ERR_SHAPE, "need 2 <= nsub <= min(n, 4096)");
+  if (!Z_raw || !Z_std || !y_raw || !sub_idx || !ws || (!stats64 && !stats32)) return fail(GPR_ERR_ARG, "null pointer");
+  if (ws_bytes < (size_t)stats_sort_len(nsub) * sizeof(double)) return fail(GPR_ERR_WORKSPACE, "workspace too small");
+  HIPCHK(launch_summary_stats(Z_raw, Z_std, y_raw, n, d, sub_idx, nsub, (double*)ws, stats64, stats32,
+                              (hipStream_t)stream));
+  return GPR_OK;
+}
+
+GPR_API int gpr_mlp_nparams(void) { return mlp_nparams(); }
+
+GPR_API int gpr_mlp_workspace(int64_t batch, size_t* bytes) {
+  if (batch < 1 || batch > 65536 || !bytes) return fail(GPR_ERR_ARG, "need 1 <= batch <= 65536 and bytes");
+  *bytes = (mlp_act_floats((int)batch) + (size_t)mlp_nparams()) * sizeof(float) + 512;
+  return GPR_OK;
+}
+
+static int mlp_check(int64_t batch, void* ws, size_t ws_bytes) {
+  if (batch < 1 || batch > 65536) return fail(GPR_ERR_SHAPE, "need 1 <= batch <= 65536");
+  if (!ws) return fail(GPR_ERR_ARG, "null workspace");
+  if (ws_bytes < (mlp_act_floats((int)batch) + (size_t)mlp_nparams()) * sizeof(float))
+    return fail(GPR_ERR_WORKSPACE, "workspace too small");
+  return GPR_OK;
+}
+
+GPR_API int gpr_mlp_forward(const float* params, const float* X, int64_t batch, float* out, void* ws, size_t ws_bytes,
+                            void* stream) {
+  int rc;
+  if ((rc = mlp_check(batch, ws, ws_bytes))) return rc;
+  if (!params || !X || !out) return fail(GPR_ERR_ARG, "null pointer");
+  HIPCHK(launch_mlp(const_cast<float*>(params), nullptr, nullptr, nullptr, X, nullptr, out, nullptr, (float*)ws,
+                    (int)batch, 0, 0.f, 0.f, 0.f, 0.f, 0, (hipStream_t)stream));
+  return GPR_OK;
+}
+
+GPR_API int gpr_mlp_loss_grad(const float* params, const float* X, const float* Y, int64_t batch, float* loss,
+                              float* grad, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = mlp_check(batch, ws, ws_bytes))) return rc;
+  if (!params || !X || !Y || !grad) return fail(GPR_ERR_ARG, "null pointer");
+  HIPCHK(launch_mlp(const_cast<float*>(params), nullptr, nullptr, grad, X, Y, nullptr, loss, (float*)ws, (int)batch, 1,
+                    0.f, 0.f, 0.f, 0.f, 0, (hipStream_t)stream));
+  return GPR_OK;
+}
+
+GPR_API int gpr_mlp_train_step(float* params, float* adam_m, float* adam_v, int t, const float* X, const float* Y,
+                               int64_t batch, float lr, float beta1, float beta2, float eps, float* loss, void* ws,
+                               size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = mlp_check(batch, ws, ws_bytes))) return rc;
+  if (!params || !adam_m || !adam_v || !X || !Y) return fail(GPR_ERR_ARG, "null pointer");
+  if (t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0))
+    return fail(GPR_ERR_ARG, "bad Adam parameters");
+  float* grad = (float*)ws + mlp_act_floats((int)batch);
+  HIPCHK(launch_mlp(params, adam_m, adam_v, grad, X, Y, nullptr, loss, (float*)ws, (int)batch, 2, lr, beta1, beta2,
+                    eps, t, (hipStream_t)stream));
   return GPR_OK;
 }
 

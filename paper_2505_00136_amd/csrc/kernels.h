@@ -1,5 +1,7 @@
 // Host-side launchers of the gfx950 kernels (internal; not part of the C-ABI).
 #pragma once
+#include <vector>
+
 #include "common.h"
 
 namespace gpr {
@@ -19,9 +21,11 @@ hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs,
 // hi/mid/lo bfloat16 parts (round to nearest even) of float32 x; lo may be null
 hipError_t launch_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, hipStream_t st);
 
-// potrf.hip
+// potrf_block.hip: Cholesky + inverse of one jb x jb (jb <= 64) diagonal block by one workgroup
 hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,
                               unsigned long long* info, hipStream_t st);
+
+// potrf.hip
 hipError_t launch_set_identity(double* W, int64_t b, hipStream_t st);
 hipError_t launch_zero_upper(double* A, int64_t b, hipStream_t st);
 hipError_t launch_convert_f64_f32(const double* src, float* dst, int64_t count, hipStream_t st);
@@ -70,5 +74,16 @@ hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, in
 hipError_t launch_adam3(double* theta, double* state, const double* grad, double lr, double b1, double b2,
                         double eps, int t0, int t1, int t2, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
+
+// warmstart.hip
+int64_t stats_sort_len(int64_t nsub);
+hipError_t launch_summary_stats(const double* Zraw, const double* Zstd, const double* yraw, int64_t n, int64_t d,
+                                const int64_t* sub, int64_t nsub, double* work, double* out64, float* out32,
+                                hipStream_t st);
+int mlp_nparams();
+size_t mlp_act_floats(int B);
+hipError_t launch_mlp(float* params, float* m, float* v, float* grad, const float* X, const float* Y, float* out,
+                      float* loss, float* act, int B, int mode, float lr, float b1, float b2, float eps, int t,
+                      hipStream_t st);
 
 }  // namespace gpr
