@@ -38,6 +38,40 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "update_kernel_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2505_00136_amd", "csrc", "gemm.hip")
+
+
+def source_digest(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per trailing-update launch from the committed counter record, or None when
+    the record is missing or the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != source_digest(KERNEL_SOURCE):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_calibration(nbytes: int):
+    """A plain device-to-device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}))
+
+
 def chol_flops(n: int) -> float:
     return n ** 3 / 3.0 + n ** 2 / 2.0 + n / 6.0
 
@@ -223,7 +257,7 @@ def run(args):
         "roofline": {"bound": "mfma", "kernel": "gemm_update_kernel<double> (trailing SYRK+GEMM of each step)",
                      "achieved": round(achieved, 4) if achieved else None, "peak": PEAK_TFLOPS[upd_dtype],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[upd_dtype], 4) if achieved else None,
-                     "traffic": None, "launches": launches, "avg_launch_ms": round(upd_avg_ms, 4),
+                     "traffic": recorded_traffic(), "launches": launches, "avg_launch_ms": round(upd_avg_ms, 4),
                      "avg_launch_algo_flops": upd_avg_flops},
         "results": summary,
     }
@@ -241,7 +275,12 @@ def main():
     ap.add_argument("--workload", default="n65536_d128", choices=sorted(WORKLOADS))
     ap.add_argument("--precs", default="fp64,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device copy of this many bytes (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path is a design "
                                    "(tile-cyclic sharding) and is not implemented", "n_gpus": args.gpus}))

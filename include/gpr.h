@@ -167,6 +167,50 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
                          double eps, double* adam_state, double* nlml_trace, void* K_tiles, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- learned warm start
+ * A small network maps 32 summary statistics of a dataset to initial log-hyperparameters
+ * for gpr_optimize; the default initialisation remains the fallback, chosen whenever its
+ * NLML is lower.  These calls are additions to the paper's method. */
+
+/* Workspace bytes of gpr_summary_stats for a subsample of nsub points. */
+GPR_API int gpr_stats_workspace(int64_t nsub, size_t* bytes);
+
+/* The 32 summary statistics of one dataset, in float64 (stats64[32]) and/or cast to
+ * float32 (stats32[32]); either output may be NULL:
+ *   [0:8]   quantiles at k/7, k = 0..7, of the d population variances of the raw feature columns;
+ *   [8:31]  quantiles at k/24, k = 1..23, of log |zs_i - zs_j| over all pairs i < j of the
+ *           subsample rows sub_idx[0..nsub) of the standardised features Z_std;
+ *   [31]    log of the population variance of the raw targets.
+ * Quantiles interpolate linearly between order statistics at position q (count - 1).
+ * Z_raw, Z_std: n x d float64; y_raw: n; sub_idx: nsub distinct row indices (int64, device);
+ * 1 <= d <= 256, 2 <= nsub <= min(n, 4096). */
+GPR_API int gpr_summary_stats(const double* Z_raw, const double* Z_std, const double* y_raw, int64_t n, int64_t d,
+                              const int64_t* sub_idx, int64_t nsub, double* stats64, float* stats32, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Parameter count of the network 32 -> 128 -> 128 -> 3 (exact-erf GELU after the first two
+ * layers): 21,123 float32 values in the order W1 (128x32, row-major [out][in]), b1, W2
+ * (128x128), b2, W3 (3x128), b3. */
+GPR_API int gpr_mlp_nparams(void);
+
+/* Workspace bytes of the network calls for a batch of `batch` rows. */
+GPR_API int gpr_mlp_workspace(int64_t batch, size_t* bytes);
+
+/* out[batch x 3] = network(X[batch x 32]); float32, row-major. */
+GPR_API int gpr_mlp_forward(const float* params, const float* X, int64_t batch, float* out, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Mean-squared-error loss over the batch x 3 outputs against Y (loss: device scalar or NULL)
+ * and its gradient w.r.t. the parameters (grad: 21,123 floats, out). */
+GPR_API int gpr_mlp_loss_grad(const float* params, const float* X, const float* Y, int64_t batch, float* loss,
+                              float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* One training step: loss, gradient and an Adam update (bias correction with the
+ * 1-based step t) of params, adam_m and adam_v (21,123 floats each, in/out). */
+GPR_API int gpr_mlp_train_step(float* params, float* adam_m, float* adam_v, int t, const float* X, const float* Y,
+                               int64_t batch, float lr, float beta1, float beta2, float eps, float* loss, void* ws,
+                               size_t ws_bytes, void* stream);
+
 /* The three-way bfloat16 split used by GPR_BF16X3 / GPR_BF16X6 after each panel solve:
  * hi = rne(x), mid = rne(x - hi), lo = rne(x - hi - mid), each a bfloat16 stored as
  * uint16 bits (rne = round to nearest, ties to even; the subtractions are exact in

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <mutex>
@@ -36,7 +37,8 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(GPR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int64_t kInnerBlock = 64;     // diagonal-block edge of the in-tile factorisation
+// diagonal-block edge of the in-tile factorisation (set from the environment for tuning runs only)
+constexpr int64_t kInnerBlock = 64;     // block edge of the in-tile factorisation loop
 constexpr int64_t kRowsPerChunk = 256;  // rows per workgroup of the transposed matrix-vector products
 constexpr int64_t kColsPerChunk = 4096; // training points per workgroup of the fused kernel-vector products
 
@@ -169,111 +171,132 @@ struct CholWs {
   unsigned long long* info;
   void* panel;      // copy of the panel below the diagonal tile (TRSM source)
   float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
-  uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2
+  uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2, two sets
 
   void* arena;
   size_t arena_cap;
 };
 
+void describe_diag_and_panel(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
+  const int64_t b = L.b, T = L.T;
+  const bool mixed = is_mixed(prec);
+  double* Dk = L.diag(K, k);
+  double* Wk = L.winv(K, k);
+  P.kernel([=](hipStream_t s) { return launch_set_identity(Wk, b, s); });
+  const int64_t nbk = kInnerBlock;
+  for (int64_t r0 = 0; r0 < b; r0 += nbk) {
+    const int64_t jb = std::min(nbk, b - r0), rb = r0 + jb, nbelow = b - rb;
+    P.kernel([=](hipStream_t s) { return launch_potrf_block(Dk + r0 * b + r0, b, Wk + r0 * b + r0, b, (int)jb, k * b + r0, w.info, s); });
+    P.gemm_begin(0);
+    // block row j of W: W_j[:, 0:r0] <- W_jj W_j[:, 0:r0]  (in place, column-partitioned)
+    P.job(Wk + r0 * b, b, nullptr, 0, jb, r0, 1.0, 0.0, 0);
+    P.seg(Wk + r0 * b + r0, b, MODE_KC, Wk + r0 * b, b, MODE_MC, jb, A_LOWER);
+    // block column j of L below the block: P_j = A[rb:, r0:rb] W_jj^T  (in place, row-partitioned)
+    P.job(Dk + rb * b + r0, b, nullptr, 0, nbelow, jb, 1.0, 0.0, 0);
+    P.seg(Dk + rb * b + r0, b, MODE_KC, Wk + r0 * b + r0, b, MODE_KC, jb, B_LOWER);
+    P.gemm_end();
+    if (nbelow > 0) {
+      P.gemm_begin(0);
+      // W[rb:, 0:rb] -= P_j W_j[:, 0:rb]
+      P.job(Wk + rb * b, b, Wk + rb * b, b, nbelow, rb, -1.0, 1.0, 0);
+      P.seg(Dk + rb * b + r0, b, MODE_KC, Wk + r0 * b, b, MODE_MC, jb, 0);
+      // A[rb:, rb:] -= P_j P_j^T (lower part)
+      P.job(Dk + rb * b + rb, b, Dk + rb * b + rb, b, nbelow, nbelow, -1.0, 1.0, JOB_LOWER_ONLY);
+      P.seg(Dk + rb * b + r0, b, MODE_KC, Dk + rb * b + r0, b, MODE_KC, jb, 0);
+      P.gemm_end();
+    }
+  }
+  P.kernel([=](hipStream_t s) { return launch_zero_upper(Dk, b, s); });
+  if (k == T - 1) return;
+  void* panel = L.off(K, k + 1, k);
+  const int64_t prow = (T - k - 1) * b;
+  const size_t pbytes = (size_t)prow * b * L.esize;
+  P.kernel([=](hipStream_t s) { return launch_copy(w.panel, panel, pbytes, s); });
+  if (mixed) P.kernel([=](hipStream_t s) { return launch_convert_f64_f32(Wk, w.w32, b * b, s); });
+  // TRSM: panel = panel_copy * W_kk^T
+  P.gemm_begin(mixed);
+  P.job(panel, b, nullptr, 0, prow, b, 1.0, 0.0, mixed ? JOB_C_F32 : 0);
+  P.seg(w.panel, b, MODE_KC, mixed ? (const void*)w.w32 : (const void*)Wk, b, MODE_KC, b, B_LOWER);
+  P.gemm_end();
+  if (is_bf16(prec)) {
+    const int64_t pstride = (T - 1) * b * b;
+    uint16_t* pl = w.planes + (k & 1) * 3 * pstride;
+    P.kernel([=](hipStream_t s) {
+      return launch_split_bf16x3((const float*)panel, prow * b, pl, pl + pstride,
+                                 prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr, s);
+    });
+  }
+}
+
+// Trailing update of step k restricted to block columns [n0, n1) (SYRK on diagonal tiles,
+// GEMM elsewhere).  Mixed modes: the SYRK on the float64 diagonal tiles multiplies the
+// float32 panel in float64 (exact products, so the pivots do not inherit float32
+// accumulation error); the GEMM tiles use the mode's products.
+void describe_update(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k, int64_t n0,
+                     int64_t n1) {
+  const int64_t b = L.b, T = L.T;
+  if (n0 >= n1) return;
+  const bool mixed = is_mixed(prec), split = is_bf16(prec);
+  const int64_t pstride = (T - 1) * b * b;
+  const uint16_t* pl = split ? w.planes + (k & 1) * 3 * pstride : nullptr;
+  auto opnd = [&](int64_t m) -> const void* {
+    return split ? (const void*)(pl + (m - k - 1) * b * b) : (const void*)L.off(K, m, k);
+  };
+  const double bd = (double)b;
+  double syrk_flops = 0.0, gemm_flops = 0.0;
+  for (int64_t nn = n0; nn < n1; ++nn) {
+    syrk_flops += bd * bd * (bd + 1.0);
+    gemm_flops += 2.0 * (double)(T - nn - 1) * bd * bd * bd;
+  }
+  if (mixed) {
+    P.gemm_begin(0, GEMM_KIND_WIDEN);
+    for (int64_t m = n0; m < n1; ++m) {
+      double* Cm = L.diag(K, m);
+      P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
+      P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, m, k), b, MODE_KC, b, 0);
+    }
+    P.gemm_end();
+  }
+  {
+    const int kind = !split ? GEMM_KIND_UPDATE : (prec == GPR_BF16X6 ? GEMM_KIND_BF16X6 : GEMM_KIND_BF16X3);
+    P.gemm_begin(mixed, kind, mixed ? gemm_flops : syrk_flops + gemm_flops);
+  }
+  for (int64_t nn = n0; nn < n1; ++nn) {
+    for (int64_t m = nn; m < T; ++m) {
+      if (m == nn) {
+        if (mixed) continue;
+        double* Cm = L.diag(K, m);
+        P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
+      } else {
+        void* Cmn = L.off(K, m, nn);
+        P.job(Cmn, b, Cmn, b, b, b, -1.0, 1.0, mixed ? JOB_C_F32 : 0);
+      }
+      P.seg(opnd(m), b, MODE_KC, opnd(nn), b, MODE_KC, b, 0);
+      if (split) P.segs.back().pstrideA = P.segs.back().pstrideB = pstride;
+    }
+  }
+  P.gemm_end();
+}
+
 // The tiled right-looking factorisation (Fig. 1).  Step k: factor the diagonal tile
 // and invert its factor (POTRF), X_mk = A_mk L_kk^{-T} for the panel (TRSM, one GEMM
 // against the inverse), then A_mn -= X_mk X_nk^T over the trailing lower triangle
-// (SYRK on diagonal tiles, GEMM elsewhere) as one batched launch.
+// (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.  Each step's update is
+// issued as the next block column first (U1) and the remaining columns (U2), all in
+// the caller's stream.  The split-bfloat16 planes are double-buffered by step parity.
 //
-// The diagonal tile itself is factored by a blocked right-looking loop with 64-wide
-// blocks; its inverse W is accumulated in the same loop: starting from W = I, block
+// The diagonal tile itself is factored by a blocked right-looking loop with blocks of
+// 64; its inverse W is accumulated in the same loop: starting from W = I, block
 // step j multiplies block row j of W by the block inverse W_jj and subtracts
 // P_j (W_jj W_j) from the rows below, P_j being the block column of L below the
 // diagonal block; that update shares its launch with the trailing update P_j P_j^T.
 void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w) {
-  const int64_t b = L.b, T = L.T;
-  const bool mixed = is_mixed(prec);
-  hipStream_t st = P.st;
-  for (int64_t k = 0; k < T; ++k) {
-    double* Dk = L.diag(K, k);
-    double* Wk = L.winv(K, k);
-    P.kernel([=] { return launch_set_identity(Wk, b, st); });
-    for (int64_t r0 = 0; r0 < b; r0 += kInnerBlock) {
-      const int64_t jb = std::min(kInnerBlock, b - r0), rb = r0 + jb, nbelow = b - rb;
-      P.kernel([=] { return launch_potrf_block(Dk + r0 * b + r0, b, Wk + r0 * b + r0, b, (int)jb, k * b + r0, w.info, st); });
-      P.gemm_begin(0);
-      // block row j of W: W_j[:, 0:r0] <- W_jj W_j[:, 0:r0]  (in place, column-partitioned)
-      P.job(Wk + r0 * b, b, nullptr, 0, jb, r0, 1.0, 0.0, 0);
-      P.seg(Wk + r0 * b + r0, b, MODE_KC, Wk + r0 * b, b, MODE_MC, jb, A_LOWER);
-      // block column j of L below the block: P_j = A[rb:, r0:rb] W_jj^T  (in place, row-partitioned)
-      P.job(Dk + rb * b + r0, b, nullptr, 0, nbelow, jb, 1.0, 0.0, 0);
-      P.seg(Dk + rb * b + r0, b, MODE_KC, Wk + r0 * b + r0, b, MODE_KC, jb, B_LOWER);
-      P.gemm_end();
-      if (nbelow > 0) {
-        P.gemm_begin(0);
-        // W[rb:, 0:rb] -= P_j W_j[:, 0:rb]
-        P.job(Wk + rb * b, b, Wk + rb * b, b, nbelow, rb, -1.0, 1.0, 0);
-        P.seg(Dk + rb * b + r0, b, MODE_KC, Wk + r0 * b, b, MODE_MC, jb, 0);
-        // A[rb:, rb:] -= P_j P_j^T (lower part)
-        P.job(Dk + rb * b + rb, b, Dk + rb * b + rb, b, nbelow, nbelow, -1.0, 1.0, JOB_LOWER_ONLY);
-        P.seg(Dk + rb * b + r0, b, MODE_KC, Dk + rb * b + r0, b, MODE_KC, jb, 0);
-        P.gemm_end();
-      }
-    }
-    P.kernel([=] { return launch_zero_upper(Dk, b, st); });
-    if (k == T - 1) break;
-    void* panel = L.off(K, k + 1, k);
-    const int64_t prow = (T - k - 1) * b;
-    const size_t pbytes = (size_t)prow * b * L.esize;
-    P.kernel([=] { return hipMemcpyAsync(w.panel, panel, pbytes, hipMemcpyDeviceToDevice, st); });
-    if (mixed) P.kernel([=] { return launch_convert_f64_f32(Wk, w.w32, b * b, st); });
-    // TRSM: panel = panel_copy * W_kk^T
-    P.gemm_begin(mixed);
-    P.job(panel, b, nullptr, 0, prow, b, 1.0, 0.0, mixed ? JOB_C_F32 : 0);
-    P.seg(w.panel, b, MODE_KC, mixed ? (const void*)w.w32 : (const void*)Wk, b, MODE_KC, b, B_LOWER);
-    P.gemm_end();
-    // split-bfloat16 planes of the solved panel
-    const bool split = is_bf16(prec);
-    const int64_t pstride = (T - 1) * b * b;
-    if (split) {
-      uint16_t* pl = w.planes;
-      P.kernel([=] {
-        return launch_split_bf16x3((const float*)panel, prow * b, pl, pl + pstride,
-                                   prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr, st);
-      });
-    }
-    // Trailing update.  float64: SYRK and GEMM tiles in one launch.  Mixed modes: the
-    // SYRK on the float64 diagonal tiles multiplies the float32 panel in float64 (exact
-    // products, so the pivots do not inherit float32 accumulation error); the GEMM tiles
-    // use the mode's products.
-    const double tp = (double)(T - k - 1), bd = (double)b;
-    const double syrk_flops = tp * bd * bd * (bd + 1.0), gemm_flops = tp * (tp - 1.0) * bd * bd * bd;
-    auto opnd = [&](int64_t m) -> const void* {
-      return split ? (const void*)(w.planes + (m - k - 1) * b * b) : (const void*)L.off(K, m, k);
-    };
-    if (mixed) {
-      P.gemm_begin(0, GEMM_KIND_WIDEN);
-      for (int64_t m = k + 1; m < T; ++m) {
-        double* Cm = L.diag(K, m);
-        P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
-        P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, m, k), b, MODE_KC, b, 0);
-      }
-      P.gemm_end();
-    }
-    {
-      const int kind = !split ? GEMM_KIND_UPDATE : (prec == GPR_BF16X6 ? GEMM_KIND_BF16X6 : GEMM_KIND_BF16X3);
-      P.gemm_begin(mixed, kind, mixed ? gemm_flops : syrk_flops + gemm_flops);
-    }
-    for (int64_t nn = k + 1; nn < T; ++nn) {
-      for (int64_t m = nn; m < T; ++m) {
-        if (m == nn) {
-          if (mixed) continue;
-          double* Cm = L.diag(K, m);
-          P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
-        } else {
-          void* Cmn = L.off(K, m, nn);
-          P.job(Cmn, b, Cmn, b, b, b, -1.0, 1.0, mixed ? JOB_C_F32 : 0);
-        }
-        P.seg(opnd(m), b, MODE_KC, opnd(nn), b, MODE_KC, b, 0);
-        if (split) P.segs.back().pstrideA = P.segs.back().pstrideB = pstride;
-      }
-    }
-    P.gemm_end();
+  const int64_t T = L.T;
+  describe_diag_and_panel(P, L, K, prec, w, 0);
+  for (int64_t k = 0; k + 1 < T; ++k) {
+    describe_update(P, L, K, prec, w, k, k + 1, k + 2);   // U1: block column k+1
+    describe_update(P, L, K, prec, w, k, k + 2, T);       // U2: the remaining columns
+    describe_diag_and_panel(P, L, K, prec, w, k + 1);
   }
 }
 
@@ -286,7 +309,7 @@ CholSizes chol_sizes(const TileLayout& L, int prec) {
   c.take<char>(256);
   c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   if (is_mixed(prec)) c.take<float>((size_t)L.b * L.b);
-  if (is_bf16(prec)) c.take<uint16_t>((size_t)3 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b);
+  if (is_bf16(prec)) c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b);
   Program P;
   CholWs w{};
   describe_cholesky(P, L, nullptr, prec, w);
@@ -299,7 +322,7 @@ CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
   w.info = c.take<unsigned long long>(32);
   w.panel = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.b * L.b) : nullptr;
-  w.planes = is_bf16(prec) ? c.take<uint16_t>((size_t)3 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b) : nullptr;
+  w.planes = is_bf16(prec) ? c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b) : nullptr;
   w.arena = c.take<char>(0);
   w.arena_cap = ws_bytes > c.off ? ws_bytes - c.off : 0;
   return w;

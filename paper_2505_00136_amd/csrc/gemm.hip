@@ -48,12 +48,28 @@ GPR_DEV void seg_krange(const GemmSeg& s, int m0, int n0, int& kb, int& ke) {
 }
 
 // Loads this thread's share of a 128 x 16 operand chunk into registers (zero outside
-// [0,lim) x [k0,kend)).
+// [0,lim) x [k0,kend)).  When the whole chunk is in range and the rows are 16-byte
+// aligned (a uniform test), the loads are unguarded 16-byte vector loads; otherwise
+// every element is guarded.
 template <typename T>
 GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base, int lim,
                         int k0, int kend, int tid, T (&r)[8]) {
+  constexpr int VEC = 16 / sizeof(T);   // elements per 16-byte load
+  const bool aligned = ((((uintptr_t)P) & 15) == 0) && (ld % VEC == 0);
   if (mode == MODE_KC) {
     const int kk = k0 + (tid & 7) * 2;
+    if (aligned && base + GEMM_BM <= lim && k0 + GEMM_BK <= kend && (VEC == 2)) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int row = base + (tid >> 3) + 32 * p;
+        const T* q = P + (int64_t)row * ld + kk;
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        const v2 v = *reinterpret_cast<const v2*>(q);
+        r[2 * p] = v[0];
+        r[2 * p + 1] = v[1];
+      }
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int row = base + (tid >> 3) + 32 * p;
@@ -65,8 +81,18 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
   } else {
     const int k = k0 + (tid >> 4);
     const int r0 = base + (tid & 15) * 8;
-    const bool kok = k < kend;
     const T* q = P + (int64_t)k * ld + r0;
+    if (aligned && base + GEMM_BM <= lim && k0 + GEMM_BK <= kend) {
+      typedef T vv __attribute__((ext_vector_type(VEC)));
+#pragma unroll
+      for (int e = 0; e < 8; e += VEC) {
+        const vv v = *reinterpret_cast<const vv*>(q + e);
+#pragma unroll
+        for (int x = 0; x < VEC; ++x) r[e + x] = v[x];
+      }
+      return;
+    }
+    const bool kok = k < kend;
 #pragma unroll
     for (int e = 0; e < 8; ++e) r[e] = (kok && r0 + e < lim) ? q[e] : T(0);
   }

@@ -21,7 +21,7 @@ hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs,
 // hi/mid/lo bfloat16 parts (round to nearest even) of float32 x; lo may be null
 hipError_t launch_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, hipStream_t st);
 
-// potrf_block.hip: Cholesky + inverse of one jb x jb (jb <= 64) diagonal block by one workgroup
+// potrf_block.hip: Cholesky + inverse of one jb x jb (jb <= 128) diagonal block by one workgroup
 hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,
                               unsigned long long* info, hipStream_t st);
 
@@ -29,6 +29,8 @@ hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, in
 hipError_t launch_set_identity(double* W, int64_t b, hipStream_t st);
 hipError_t launch_zero_upper(double* A, int64_t b, hipStream_t st);
 hipError_t launch_convert_f64_f32(const double* src, float* dst, int64_t count, hipStream_t st);
+// device copy with a kernel on `st` (16-byte vectors when aligned)
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 
 // assemble.hip
 // Lower tiles of K (Eq. 2) into the tiled layout: region D (float64) and region O (esize 8 or 4).

@@ -1,78 +1,112 @@
-// Factorisation and inversion of one 64 x 64 diagonal block by one workgroup in LDS.
+// Factorisation and inversion of one diagonal block (up to 128 x 128) by one workgroup.
 //
 // The diagonal tile of each step of the tiled factorisation (the POTRF task of
-// Fig. 1) is factored by a blocked right-looking loop over 64-wide blocks (the
+// Fig. 1) is factored by a blocked right-looking loop over 64- or 128-wide blocks (the
 // orchestration issues the block steps in stream order); this kernel handles the
-// diagonal block of each block step: the unblocked right-looking Cholesky (four
-// threads per row) and the inverse of the factor by row operations on the identity,
-// both with one barrier-separated phase per column.
+// diagonal block of each block step.  The block and its inverse live in registers:
+// 4 threads per row, thread t owns row t/4 and every fourth column starting at t%4, of
+// both L and W = L^{-1}.  One loop over the columns j does, with two barriers:
+//   pivot  L_jj = sqrt(A_jj), column j of L scaled by 1/L_jj, row j of W scaled by 1/L_jj,
+//   then   A_ik -= L_ij L_kj  (j < k <= i)  and  W_ic -= L_ij W_jc  (c <= j < i),
+// i.e. the right-looking Cholesky fused with forward elimination of L W = I.
+// Column j of L and row j of W are exchanged through LDS; the next pivot column is
+// handed over in LDS by the threads that update it, and column k of L keeps its
+// unscaled value in registers until the final store applies 1/L_kk, so no register is
+// indexed at run time and no global store is pending at any barrier.
 #include "common.h"
 #include "kernels.h"
 
 namespace gpr {
 
-constexpr int DB = 64;           // block edge
-// Cholesky of the jb x jb block at A (in place, zero upper) and its inverse into W.
-// a and w are LDS scratch of DB x (DB+1).
-GPR_DEV void potrf_inv_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,
-                             unsigned long long* info, double (*a)[DB + 1], double (*w)[DB + 1]) {
+// Block edge PB (64 or 128), PB*4 threads; thread t owns row t/4 and columns t%4 + 4q.
+template <int PB>
+__global__ __launch_bounds__(PB * 4)
+void potrf_block_kernel(double* __restrict__ A, int64_t lda, double* __restrict__ W, int64_t ldw, int jb,
+                        int64_t col_base, unsigned long long* info) {
+  constexpr int PQ = PB / 4;
+  // exchange vector of step j, element k: L_kj (k > j) or W_jk (k <= j) -- the two ranges
+  // never overlap.  Stored as ex[k % 4][k / 4] so that each thread's operands are contiguous.
+  __shared__ __align__(16) double ex[4][PQ];
+  __shared__ double nextc[PB];    // current column j of A, before scaling
+  __shared__ double piv[PB];
+  __shared__ double ipiv[PB];
   const int tid = threadIdx.x;
-  for (int e = tid; e < DB * DB; e += 256) {
-    const int i = e / DB, k = e % DB;
-    a[i][k] = (i < jb && k <= i) ? A[(int64_t)i * lda + k] : 0.0;
-    w[i][k] = (i == k && i < jb) ? 1.0 : 0.0;
+  const int i = tid >> 2, cq = tid & 3;
+  double ra[PQ], rw[PQ];
+#pragma unroll
+  for (int q = 0; q < PQ; ++q) {
+    const int k = cq + 4 * q;
+    ra[q] = (i < jb && k <= i) ? A[(int64_t)i * lda + k] : 0.0;
+    rw[q] = (i < jb && k == i) ? 1.0 : 0.0;
+  }
+  if (cq == 0 && i < jb) nextc[i] = ra[0];
+  __syncthreads();
+  for (int j = 0; j < jb; ++j) {
+    if (i == j && cq == (j & 3)) {
+      const double d = nextc[j];
+      if (!(d > 0.0)) atomicMin(info, (unsigned long long)(col_base + j + 1));
+      const double p = sqrt(d);
+      piv[j] = p;
+      ipiv[j] = 1.0 / p;
+    }
+    __syncthreads();
+    const double inv = ipiv[j];
+    if (cq == 0 && i > j && i < jb) ex[i & 3][i >> 2] = nextc[i] * inv;     // column j of L
+    if (i == j) {                                                             // row j of W is final
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int c = cq + 4 * q;
+        const double v = rw[q] * inv;
+        rw[q] = c <= j ? v : rw[q];
+        ex[cq][q] = c <= j ? v : ex[cq][q];
+      }
+    }
+    __syncthreads();
+    if (i > j && i < jb) {
+      const double li = ex[i & 3][i >> 2];
+      double e[PQ];
+#pragma unroll
+      for (int q = 0; q < PQ; q += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(&ex[cq][q]);
+        e[q] = v.x;
+        e[q + 1] = v.y;
+      }
+      const int j1 = j + 1;
+      double nv = 0.0;
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int k = cq + 4 * q;
+        const double ma = (k > j && k <= i) ? li : 0.0;
+        const double mw = (k <= j) ? li : 0.0;
+        ra[q] = fma(-ma, e[q], ra[q]);
+        rw[q] = fma(-mw, e[q], rw[q]);
+        nv = (k == j1) ? ra[q] : nv;
+      }
+      if (cq == (j1 & 3)) nextc[i] = nv;
+    }
   }
   __syncthreads();
-  // right-looking unblocked Cholesky; 4 threads per row, columns strided by 4
-  const int ri = tid >> 2, cq = tid & 3;
-  for (int j = 0; j < jb; ++j) {
-    const double dj = a[j][j];
-    const double piv = sqrt(dj);
-    if (tid == 0 && !(dj > 0.0)) atomicMin(info, (unsigned long long)(col_base + j + 1));
-    const double inv = 1.0 / piv;
-    __syncthreads();
-    if (cq == 0 && ri > j && ri < jb) a[ri][j] *= inv;
-    if (tid == 0) a[j][j] = piv;
-    __syncthreads();
-    if (ri > j && ri < jb) {
-      const double lij = a[ri][j];
-      for (int k = j + 1 + cq; k <= ri; k += 4) a[ri][k] -= lij * a[k][j];
+  // column k of L kept its unscaled value in the registers since step k
+#pragma unroll
+  for (int q = 0; q < PQ; ++q) {
+    const int k = cq + 4 * q;
+    if (i < jb && k < jb) {
+      A[(int64_t)i * lda + k] = k < i ? ra[q] * ipiv[k] : (k == i ? piv[k] : 0.0);
+      W[(int64_t)i * ldw + k] = k <= i ? rw[q] : 0.0;
     }
-    __syncthreads();
-  }
-  // inverse by row operations on W = I: row j /= L_jj, then row i -= L_ij row j (i > j)
-  for (int j = 0; j < jb; ++j) {
-    const double inv = 1.0 / a[j][j];
-    if (ri == j) {
-      for (int c = cq; c <= j; c += 4) w[j][c] *= inv;
-    }
-    __syncthreads();
-    if (ri > j && ri < jb) {
-      const double lij = a[ri][j];
-      for (int c = cq; c <= j; c += 4) w[ri][c] -= lij * w[j][c];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int i = e / jb, k = e % jb;
-    A[(int64_t)i * lda + k] = k <= i ? a[i][k] : 0.0;
-    W[(int64_t)i * ldw + k] = k <= i ? w[i][k] : 0.0;
   }
 }
 
-__global__ __launch_bounds__(256)
-void potrf_block_kernel(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,
-                         unsigned long long* info) {
-  __shared__ double a[DB][DB + 1];
-  __shared__ double w[DB][DB + 1];
-  potrf_inv_block(A, lda, W, ldw, jb, col_base, info, a, w);
-}
 
 hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,
-                               unsigned long long* info, hipStream_t st) {
+                              unsigned long long* info, hipStream_t st) {
   if (jb <= 0) return hipSuccess;
-  if (jb > DB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(potrf_block_kernel, dim3(1), dim3(256), 0, st, A, lda, W, ldw, jb, col_base, info);
+  if (jb <= 64)
+    hipLaunchKernelGGL(potrf_block_kernel<64>, dim3(1), dim3(256), 0, st, A, lda, W, ldw, jb, col_base, info);
+  else if (jb <= 128)
+    hipLaunchKernelGGL(potrf_block_kernel<128>, dim3(1), dim3(512), 0, st, A, lda, W, ldw, jb, col_base, info);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

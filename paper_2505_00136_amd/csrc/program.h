@@ -41,7 +41,7 @@ inline TimingLog g_timing;
 
 struct Program {
   bool exec = false;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;        // the caller's stream
   std::vector<GemmJob> jobs;
   std::vector<GemmSeg> segs;
   const GemmJob* djobs = nullptr;
@@ -51,6 +51,8 @@ struct Program {
   int job0 = 0, nwg = 0, f32 = 0, kind = 0;
   double kind_flops = 0.0;
   bool cur_valid = false;
+
+  hipStream_t stream() const { return st; }
 
   void reset_for_exec(const GemmJob* dj, const GemmSeg* ds) {
     exec = true;
@@ -122,19 +124,20 @@ struct Program {
         timed = ea && eb;
       }
     }
-    if (timed) (void)hipEventRecord(ea, st);
-    err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, st);
+    hipStream_t sx = stream();
+    if (timed) (void)hipEventRecord(ea, sx);
+    err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, sx);
     if (timed) {
-      (void)hipEventRecord(eb, st);
+      (void)hipEventRecord(eb, sx);
       std::lock_guard<std::mutex> lk(g_timing.mu);
       const int tk = kind == GEMM_KIND_BF16X3 ? 2 : kind == GEMM_KIND_BF16X6 ? 3 : (f32 ? 1 : 0);
       g_timing.recs.push_back({ea, eb, kind_flops, tk});
     }
   }
-  // Launches produced by `fn` run only in the execute pass.
-  void kernel(const std::function<hipError_t()>& fn) {
+  // Launches produced by `fn` (given the current stream) run only in the execute pass.
+  void kernel(const std::function<hipError_t(hipStream_t)>& fn) {
     if (!exec || err != hipSuccess) return;
-    err = fn();
+    err = fn(stream());
   }
 };
 
