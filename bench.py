@@ -8,10 +8,12 @@ in HBM before the timed region; every phase is timed with HIP events on the stre
 the library launches on.
 
 Prints one JSON line.  ``value`` is the float64 Cholesky rate, (n^3/3 + n^2/2 + n/6)
-flops divided by the time of gpr_cholesky.  ``roofline`` covers the dominant kernel,
-the trailing SYRK + GEMM update of each factorisation step, from the library's event
-hook (algorithmic flops per launch / average launch duration).  ``cpu_baseline`` is
-the FP64 CPU oracle timed on the host on a bounded sample of the same workload.
+flops divided by the time of gpr_cholesky.  ``roofline`` covers the dominant kernel of
+the float64 path (the timed tile-GEMM kernel with the most time over the timed steps:
+the Cholesky trailing update, the inversion steps or the K^-1 trace products of the
+gradient), from the library's event hook: algorithmic flops per launch / average launch
+duration; ``kernels`` lists the same figures for every timed kernel.  ``cpu_baseline``
+is the FP64 CPU oracle timed on the host on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -38,8 +40,22 @@ WORKLOADS = {
 }
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "update_kernel_traffic.json")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gemm_kernel_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2505_00136_amd", "csrc", "gemm.hip")
+# timing kinds of the library's event hook -> kernel symbol, operand dtype
+TIMED_KERNELS = {
+    "fp64": ("gemm_update_kernel<double>", "f64"), "fp32": ("gemm_update_kernel<float>", "f32"),
+    "fp64_trtri": ("gemm_trtri_kernel<double>", "f64"), "fp32_trtri": ("gemm_trtri_kernel<float>", "f32"),
+    "fp64_trace": ("gemm_trace_kernel<double>", "f64"), "fp32_trace": ("gemm_trace_kernel<float>", "f32"),
+    "bf16x3": ("gemm_bf16x_kernel<3>", "bf16"), "bf16x6": ("gemm_bf16x_kernel<6>", "bf16"),
+}
+KIND_ROLE = {"fp64": "trailing SYRK+GEMM update of a Cholesky step", "fp32": "trailing SYRK+GEMM update of a Cholesky step",
+             "fp64_trtri": "step of the triangular inversion L^-1 (gradient)",
+             "fp32_trtri": "step of the triangular inversion L^-1 (gradient)",
+             "fp64_trace": "K^-1 block-row product fused with the gradient reduction",
+             "fp32_trace": "K^-1 block-row product fused with the gradient reduction",
+             "bf16x3": "trailing update of a Cholesky step from split-bf16 planes",
+             "bf16x6": "trailing update of a Cholesky step from split-bf16 planes"}
 
 
 def source_digest(path: str) -> str:
@@ -48,9 +64,9 @@ def source_digest(path: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per trailing-update launch from the committed counter record, or None when
-    the record is missing or the kernel source changed since the counters were taken."""
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter record, or None when the
+    record is missing, does not cover the kernel, or the kernel source changed since."""
     try:
         with open(TRAFFIC_RECORD) as f:
             rec = json.load(f)
@@ -58,7 +74,7 @@ def recorded_traffic():
         return None
     if rec.get("kernel_source_sha256_16") != source_digest(KERNEL_SOURCE):
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", {}).get(kernel)
 
 
 def copy_calibration(nbytes: int):
@@ -201,7 +217,7 @@ def run(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     _lib.gpr_timing_enable(False)
-    upd = {p: _lib.gpr_timing_read(p) for p in precs}
+    upd = {k: _lib.gpr_timing_read(k) for k in TIMED_KERNELS}
     K_ = args.steps
     per = {k: v / K_ for k, v in totals.items()}
 
@@ -230,15 +246,27 @@ def run(args):
         summary[p]["nlml"] = float(res[p]["nlml"][0])
 
     main = "fp64" if "fp64" in summary else precs[0]
+    kernels = {}
+    for kind, (sym, kdt) in TIMED_KERNELS.items():
+        if kind not in upd:
+            continue
+        cnt, ms_, fl_ = upd[kind]
+        if not cnt:
+            continue
+        tf = fl_ / (ms_ / 1e3) / 1e12
+        kernels[sym] = {"kind": kind, "role": KIND_ROLE[kind], "launches": cnt, "total_ms": round(ms_, 3),
+                        "avg_launch_ms": round(ms_ / cnt, 4), "avg_launch_algo_flops": fl_ / cnt,
+                        "achieved_tflops": round(tf, 4), "peak_tflops": PEAK_TFLOPS[kdt],
+                        "frac": round(tf / PEAK_TFLOPS[kdt], 4), "dtype": kdt}
     for p in precs:
-        cnt, ms_, fl_ = upd[p]
-        summary[p]["update_kernel"] = {"launches": cnt, "avg_ms": ms_ / max(cnt, 1),
-                                       "tflops": fl_ / (ms_ / 1e3) / 1e12 if cnt else None}
-    launches, upd_ms, upd_flops = upd[main]
-    upd_avg_ms = upd_ms / max(launches, 1)
-    upd_avg_flops = upd_flops / max(launches, 1)
-    achieved = upd_avg_flops / (upd_avg_ms / 1e3) / 1e12 if launches else None
-    upd_dtype = "f64" if main == "fp64" else "f32"
+        k = kernels.get(TIMED_KERNELS[p][0]) if p in TIMED_KERNELS else None
+        if k:
+            summary[p]["update_kernel"] = {"launches": k["launches"], "avg_ms": k["avg_launch_ms"],
+                                           "tflops": k["achieved_tflops"]}
+    # the dominant kernel of the float64 path: most time over the timed steps
+    main_syms = [TIMED_KERNELS[k][0] for k in TIMED_KERNELS if k.split("_")[0] == main and TIMED_KERNELS[k][0] in kernels]
+    dom = max(main_syms, key=lambda m: kernels[m]["total_ms"]) if main_syms else None
+    dk = kernels.get(dom, {})
     line = {
         "metric": METRIC,
         "value": round(summary[main]["cholesky_tflops"], 4),
@@ -254,11 +282,12 @@ def run(args):
         "data": "synthetic (seeded mass-spring-damper NFIR regressors)",
         "config": {"workload": f"{args.workload}: n_train={n}, n_test={m}, D={D}, tile={tile}, "
                                f"SE kernel l=sqrt(D), nu=1, sigma^2=0.01", "precisions": precs},
-        "roofline": {"bound": "mfma", "kernel": "gemm_update_kernel<double> (trailing SYRK+GEMM of each step)",
-                     "achieved": round(achieved, 4) if achieved else None, "peak": PEAK_TFLOPS[upd_dtype],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[upd_dtype], 4) if achieved else None,
-                     "traffic": recorded_traffic(), "launches": launches, "avg_launch_ms": round(upd_avg_ms, 4),
-                     "avg_launch_algo_flops": upd_avg_flops},
+        "roofline": {"bound": "mfma", "kernel": f"{dom} ({dk.get('role')})" if dom else None,
+                     "achieved": dk.get("achieved_tflops"), "peak": dk.get("peak_tflops"),
+                     "unit": "TFLOP/s", "frac": dk.get("frac"),
+                     "traffic": recorded_traffic(dom) if dom else None, "launches": dk.get("launches"),
+                     "avg_launch_ms": dk.get("avg_launch_ms"), "avg_launch_algo_flops": dk.get("avg_launch_algo_flops")},
+        "kernels": kernels,
         "results": summary,
     }
     if not args.no_cpu_baseline:

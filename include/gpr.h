@@ -219,16 +219,24 @@ GPR_API int gpr_mlp_train_step(float* params, float* adam_m, float* adam_v, int 
 GPR_API int gpr_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, void* stream);
 
 /* Profiling hook: while enabled, every trailing-update launch of gpr_cholesky (the
- * batched SYRK + GEMM of one factorisation step) is bracketed by HIP events on the
- * call's stream.  Host only; not needed for computing anything. */
+ * batched SYRK + GEMM of one factorisation step) and every inversion and trace launch of
+ * gpr_nlml_grad is bracketed by HIP events on the call's stream.  Host only; not needed
+ * for computing anything. */
 GPR_API int gpr_timing_enable(int on);
 
-/* Waits for the recorded events of one kind of trailing update (kind = 0: float64,
- * 1: float32, 2: bf16x3, 3: bf16x6) and returns, since the last read of that kind: the
- * number of launches, their summed duration (ms) and their algorithmic flops (per
- * step with T' = T-k-1 remaining tiles: T' b^2 (b+1) for the SYRKs plus T'(T'-1) b^3
- * for the GEMMs; the mixed kinds cover the GEMM tiles only, their diagonal-tile SYRK
- * runs as a separate float64 launch).  Resets that kind's record.  All three are host outputs. */
+/* Waits for the recorded events of one kind of timed tile-GEMM launch and returns, since
+ * the last read of that kind: the number of launches, their summed duration (ms) and
+ * their algorithmic flops.  Kinds:
+ *   0/1  float64/float32 trailing update of the Cholesky (per step with T' = T-k-1
+ *        remaining tiles: T' b^2 (b+1) for the SYRKs plus T'(T'-1) b^3 for the GEMMs;
+ *        the float32 kind covers the GEMM tiles only, the diagonal-tile SYRK of the mixed
+ *        modes runs as a separate float64 launch);
+ *   2/3  bf16x3/bf16x6 trailing update (GEMM tiles only, as kind 1);
+ *   4/5  float64/float32 step of the triangular inversion of the gradient (b^2 (b+1) per
+ *        triangular tile product, 2 b^3 per full one);
+ *   6/7  float64/float32 K^{-1} product fused with the gradient reduction (as kind 4/5;
+ *        b (b+1)(2b+1)/3 for the product of two triangular tiles).
+ * Resets that kind's record.  All three are host outputs. */
 GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops);
 
 /* Task census of the tiled Cholesky with T tiles per dimension as scheduled by this

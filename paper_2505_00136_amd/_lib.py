@@ -238,11 +238,12 @@ def gpr_mlp_train_step(params, adam_m, adam_v, t, X, Y, batch, lr, beta1, beta2,
                                      beta2, eps, _ptr(loss), _ptr(ws), ws_bytes, _stream(stream)))
 
 
-TIMING_KINDS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+TIMING_KINDS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp64_trtri": 4, "fp32_trtri": 5,
+                "fp64_trace": 6, "fp32_trace": 7}
 
 
 def gpr_timing_read(kind="fp64"):
-    """(launches, total_ms, algorithmic_flops) of one kind of trailing-update launch since the last read."""
+    """(launches, total_ms, algorithmic_flops) of one kind of timed tile-GEMM launch since the last read."""
     n, ms, fl = _i64(), _dbl(), _dbl()
     k = TIMING_KINDS[kind] if isinstance(kind, str) else int(kind)
     _check(load().gpr_timing_read(k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))

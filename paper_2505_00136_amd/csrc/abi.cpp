@@ -147,7 +147,7 @@ int upload_tables(const Program& P, void* arena, size_t cap, hipStream_t st, con
 
 // Runs a program description: record pass, table upload into `arena`, execute pass.
 template <typename F>
-int run_program(F&& describe, void* arena, size_t arena_cap, hipStream_t st) {
+int run_program(F&& describe, void* arena, size_t arena_cap, hipStream_t st, int64_t* trace_wg = nullptr) {
   Program P;
   P.st = st;
   describe(P);
@@ -162,6 +162,7 @@ int run_program(F&& describe, void* arena, size_t arena_cap, hipStream_t st) {
   describe(P);
   if (P.jobs.size() != nj || P.segs.size() != ns) return fail(GPR_ERR_HIP, "internal: record and execute passes differ");
   if (P.err != hipSuccess) return fail(GPR_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(P.err));
+  if (trace_wg) *trace_wg = P.trace_wg;
   return GPR_OK;
 }
 
@@ -451,72 +452,110 @@ VarWs carve_var(Carve& c, const TileLayout& L, int64_t m, int prec) {
 
 // ================================================================ gradient
 struct GradWs {
-  void* tmp;        // (T-1) b x b tiles
+  void* panel;      // copy of one block column of L: (T-1) b x b tiles
+  void* row;        // copy of one block row of the residual: (T-1) b x b tiles
   float* w32;       // T b x b (mixed)
-  double* partial;  // [workgroups][3]
+  double* partial;  // [trace workgroups][3]
+  int64_t partial_wg;
+  double* u;        // r^2 / (2 l^2) of every lower tile pair: T (T+1) / 2 float64 tiles
   void* arena;
 };
 
-// L^{-1} in place over region O, column by column from the right: with the trailing
-// part already inverted, Tmp_i = sum_{k=j+1..i} W_ik L_kj and W_ij = -Tmp_i W_jj.
+// Number of workgroups of all gradient-trace launches (one per macro tile of every job).
+int64_t trace_workgroups(const TileLayout& L) {
+  const int64_t tpt = ceil_div(L.b, GEMM_BM) * ceil_div(L.b, GEMM_BN);
+  return L.T * (L.T + 1) * (L.T + 2) / 6 * tpt;
+}
+
+// X = L^{-1} in place over region O, right-looking in the order of forward substitution
+// (X_jj = L_jj^{-1} is region W).  R holds the running right-hand side of L X = I; step j
+//   finalises block row j:     X_jc = L_jj^{-1} R_jc                  (c < j)
+//   eliminates block column j: R_ic -= L_ij X_jc (c < j), R_ij = -L_ij L_jj^{-1}  (i > j)
+// Each step is one launch of single-segment tile products sharing block row j and the
+// copied block column j, so concurrently running workgroups reuse the same operands.
 void describe_trtri(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
   const int64_t b = L.b, T = L.T;
   const bool mixed = is_mixed(prec);
-  const int es = mixed ? 4 : 8;
+  const size_t tb = (size_t)b * b * (mixed ? 4 : 8);
   const int cflag = mixed ? JOB_C_F32 : 0;
+  const double bd = (double)b, trmm = bd * bd * (bd + 1.0), gemm = 2.0 * bd * bd * bd;
   auto Wd = [&](int64_t i) -> const void* {
     return mixed ? (const void*)(w.w32 + (size_t)i * b * b) : (const void*)L.winv(K, i);
   };
-  for (int64_t j = T - 2; j >= 0; --j) {
-    P.gemm_begin(mixed);
-    for (int64_t i = j + 1; i < T; ++i) {
-      char* Ti = (char*)w.tmp + (size_t)(i - j - 1) * b * b * es;
-      P.job(Ti, b, nullptr, 0, b, b, 1.0, 0.0, cflag);
-      for (int64_t k = j + 1; k <= i; ++k) {
-        if (k < i) P.seg(L.off(K, i, k), b, MODE_KC, L.off(K, k, j), b, MODE_MC, b, 0);
-        else P.seg(Wd(i), b, MODE_KC, L.off(K, k, j), b, MODE_MC, b, A_LOWER);
+  for (int64_t j = 0; j < T; ++j) {
+    if (j > 0) {
+      for (int64_t c = 0; c < j; ++c) {
+        void* dst = (char*)w.row + c * tb;
+        const void* src = L.off(K, j, c);
+        P.kernel([=](hipStream_t s) { return launch_copy(dst, src, tb, s); });
       }
+      P.gemm_begin(mixed, GEMM_KIND_TRTRI, (double)j * trmm);
+      for (int64_t c = 0; c < j; ++c) {
+        P.job(L.off(K, j, c), b, nullptr, 0, b, b, 1.0, 0.0, cflag);
+        P.seg(Wd(j), b, MODE_KC, (char*)w.row + c * tb, b, MODE_MC, b, A_LOWER);
+      }
+      P.gemm_end();
     }
-    P.gemm_end();
-    P.gemm_begin(mixed);
-    P.job(L.off(K, j + 1, j), b, nullptr, 0, (T - j - 1) * b, b, -1.0, 0.0, cflag);
-    P.seg(w.tmp, b, MODE_KC, Wd(j), b, MODE_MC, b, B_UPPER);
+    if (j == T - 1) break;
+    const void* col = L.off(K, j + 1, j);
+    const size_t cbytes = (size_t)(T - j - 1) * tb;
+    P.kernel([=](hipStream_t s) { return launch_copy(w.panel, col, cbytes, s); });
+    P.gemm_begin(mixed, GEMM_KIND_TRTRI, (double)(T - j - 1) * ((double)j * gemm + trmm));
+    for (int64_t i = j + 1; i < T; ++i) {
+      const void* Pi = (const char*)w.panel + (i - j - 1) * tb;
+      for (int64_t c = 0; c < j; ++c) {
+        void* C = L.off(K, i, c);
+        P.job(C, b, C, b, b, b, -1.0, 1.0, cflag);
+        P.seg(Pi, b, MODE_KC, L.off(K, j, c), b, MODE_MC, b, 0);
+      }
+      P.job(L.off(K, i, j), b, nullptr, 0, b, b, -1.0, 0.0, cflag);
+      P.seg(Pi, b, MODE_KC, Wd(j), b, MODE_MC, b, B_UPPER);
+    }
     P.gemm_end();
   }
 }
 
-// (K^{-1})_ij = sum_{k >= i} W_ki^T W_kj for every lower tile pair, consumed by the fused
-// gradient reduction (no K^{-1} tile is stored).
+// K^{-1} = sum_k X_k^T X_k over the block rows X_k of X = L^{-1}: step k adds X_ki^T X_kj
+// to every lower tile pair j <= i <= k, and the trace epilogue contracts that contribution
+// with the gradient weights at once, so no K^{-1} tile is stored; alpha alpha^T is
+// subtracted once per tile pair, in the step k = i.  One launch per k, all of whose jobs
+// share block row k.
 void describe_lauum_trace(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
   const int64_t b = L.b, T = L.T;
   const bool mixed = is_mixed(prec);
+  const double bd = (double)b;
+  const double full = 2.0 * bd * bd * bd, tri1 = bd * bd * (bd + 1.0), tri2 = bd * (bd + 1.0) * (2.0 * bd + 1.0) / 3.0;
   auto Wd = [&](int64_t i) -> const void* {
     return mixed ? (const void*)(w.w32 + (size_t)i * b * b) : (const void*)L.winv(K, i);
   };
-  P.gemm_begin(mixed);
-  for (int64_t i = 0; i < T; ++i) {
-    for (int64_t j = 0; j <= i; ++j) {
-      P.job(nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, 0, (int)i, (int)j);
-      for (int64_t k = i; k < T; ++k) {
-        const void* A = (k == i) ? Wd(i) : L.off(K, k, i);
-        const void* B = (k == j) ? Wd(j) : L.off(K, k, j);
+  for (int64_t k = 0; k < T; ++k) {
+    const double kd = (double)k;
+    P.gemm_begin(mixed, GEMM_KIND_TRACE, kd * (kd + 1.0) / 2.0 * full + kd * tri1 + tri2);
+    for (int64_t i = 0; i <= k; ++i) {
+      const void* A = (i == k) ? Wd(k) : L.off(K, k, i);
+      for (int64_t j = 0; j <= i; ++j) {
+        const void* Bp = (j == k) ? Wd(k) : L.off(K, k, j);
         int tri = 0;
-        if (k == i) tri |= A_UPPER;
-        if (k == j) tri |= B_UPPER;
-        P.seg(A, b, MODE_MC, B, b, MODE_MC, b, tri);
+        if (i == k) tri |= A_UPPER;
+        if (j == k) tri |= B_UPPER;
+        P.job(nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, i == k ? JOB_TRACE_ALPHA : 0, (int)i, (int)j);
+        P.seg(A, b, MODE_MC, Bp, b, MODE_MC, b, tri);
       }
     }
+    P.gemm_end();
   }
-  // the launch itself is issued by the caller (trace epilogue)
 }
 
 GradWs carve_grad(Carve& c, const TileLayout& L, int prec) {
   GradWs w{};
   const int es = is_mixed(prec) ? 4 : 8;
-  w.tmp = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * es);
+  const size_t tiles = (size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * es;
+  w.panel = c.take<char>(tiles);
+  w.row = c.take<char>(tiles);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.T * L.b * L.b) : nullptr;
-  const int64_t tpt = ceil_div(L.b, GEMM_BM) * ceil_div(L.b, GEMM_BN);
-  w.partial = c.take<double>((size_t)(L.T * (L.T + 1) / 2) * tpt * 3 + 3);
+  w.partial_wg = trace_workgroups(L);
+  w.partial = c.take<double>((size_t)w.partial_wg * 3 + 3);
+  w.u = c.take<double>((size_t)(L.T * (L.T + 1) / 2) * L.b * L.b);
   w.arena = c.take<char>(0);
   return w;
 }
@@ -526,25 +565,23 @@ int grad_impl(const double* Z, int64_t d, HyperArg h, void* K, const TileLayout&
   Carve c(ws);
   GradWs w = carve_grad(c, L, prec);
   const size_t fixed = c.off;
+  const size_t cap = ws_bytes > fixed ? ws_bytes - fixed : 0;
   const bool mixed = is_mixed(prec);
   if (mixed) HIPCHK(launch_convert_f64_f32(L.winv(K, 0), w.w32, L.T * L.b * L.b, st));
-  int rc = run_program([&](Program& P) { describe_trtri(P, L, K, prec, w); }, w.arena,
-                       ws_bytes > fixed ? ws_bytes - fixed : 0, st);
+  int rc = run_program([&](Program& P) { describe_trtri(P, L, K, prec, w); }, w.arena, cap, st);
   if (rc) return rc;
-  // LAUUM + trace: record, upload, launch with the trace epilogue
-  Program P;
-  P.st = st;
-  describe_lauum_trace(P, L, K, prec, w);
-  const size_t nj = P.jobs.size();
-  const GemmJob* dj = nullptr;
-  const GemmSeg* ds = nullptr;
-  if (nj) {
-    rc = upload_tables(P, w.arena, ws_bytes > fixed ? ws_bytes - fixed : 0, st, &dj, &ds);
-    if (rc) return rc;
-    TraceArgs ta{Z, d, alpha, h, L.b, w.partial};
-    HIPCHK(launch_gemm_trace(mixed, dj, ds, (int)nj, P.nwg, ta, st));
-  }
-  HIPCHK(launch_grad_finish(w.partial, P.nwg, h, tr[0], tr[1], tr[2], grad, st));
+  HIPCHK(launch_halfdist_tiles(Z, d, h, L.b, L.T, w.u, st));
+  const TraceArgs ta{w.u, alpha, h, L.b, w.partial};
+  int64_t nwg = 0;
+  rc = run_program(
+      [&](Program& P) {
+        P.trace = &ta;
+        P.trace_cap = w.partial_wg;
+        describe_lauum_trace(P, L, K, prec, w);
+      },
+      w.arena, cap, st, &nwg);
+  if (rc) return rc;
+  HIPCHK(launch_grad_finish(w.partial, nwg, h, tr[0], tr[1], tr[2], grad, st));
   return GPR_OK;
 }
 
@@ -956,7 +993,7 @@ GPR_API int gpr_timing_enable(int on) {
 
 GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops) {
   if (!launches || !total_ms || !algo_flops) return fail(GPR_ERR_ARG, "null pointer");
-  if (kind < 0 || kind > 3) return fail(GPR_ERR_ARG, "kind must be 0..3");
+  if (kind < 0 || kind > 7) return fail(GPR_ERR_ARG, "kind must be 0..7");
   std::lock_guard<std::mutex> lk(g_timing.mu);
   int64_t cnt = 0;
   double ms = 0.0, fl = 0.0;

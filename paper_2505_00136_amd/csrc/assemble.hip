@@ -57,17 +57,24 @@ GPR_DEV void sqdist_block(const double* __restrict__ A, int64_t rows, int64_t ra
   }
 }
 
+// Tile pair (ti, tj), ti >= tj, of the row-major packed lower triangle y = ti (ti+1)/2 + tj.
+GPR_DEV void pair_of(int64_t y, int64_t& ti, int64_t& tj) {
+  ti = (int64_t)((sqrt(8.0 * (double)y + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= y) ++ti;
+  while (ti * (ti + 1) / 2 > y) --ti;
+  tj = y - ti * (ti + 1) / 2;
+}
+
+// One-dimensional grid over (tile pair, 64 x 64 block of the tile), pair-major.
 __global__ __launch_bounds__(256)
 void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, TileLayout L, void* K) {
   __shared__ double za[DC][KB];
   __shared__ double zb[DC][KB];
-  const int64_t y = blockIdx.y;
-  int64_t ti = (int64_t)((sqrt(8.0 * (double)y + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= y) ++ti;
-  while (ti * (ti + 1) / 2 > y) --ti;
-  const int64_t tj = y - ti * (ti + 1) / 2;
   const int64_t nbt = (L.b + KB - 1) / KB;
-  const int64_t br = blockIdx.x / nbt, bc = blockIdx.x % nbt;
+  const int64_t y = (int64_t)blockIdx.x / (nbt * nbt), blk = (int64_t)blockIdx.x % (nbt * nbt);
+  int64_t ti, tj;
+  pair_of(y, ti, tj);
+  const int64_t br = blk / nbt, bc = blk % nbt;
   const int64_t r0 = br * KB, c0 = bc * KB;   // within the tile
   double r2[4][4];
   sqdist_block(Z + ti * L.b * d, L.b, r0, Z + tj * L.b * d, L.b, c0, d, za, zb, r2);
@@ -95,6 +102,37 @@ void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, 
       } else {
         ((float*)Ot)[r * L.b + c] = (float)v;
       }
+    }
+  }
+}
+
+// u = r^2 / (2 l^2) for every lower tile pair, float64, pair tiles packed row-major
+// (pair y = ti (ti+1)/2 + tj at U + y b^2): the squared distances of the gradient
+// reduction, regenerated from Z once per gradient call.
+__global__ __launch_bounds__(256)
+void halfdist_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, int64_t b, double* __restrict__ U) {
+  __shared__ double za[DC][KB];
+  __shared__ double zb[DC][KB];
+  const int64_t nbt = (b + KB - 1) / KB;
+  const int64_t y = (int64_t)blockIdx.x / (nbt * nbt), blk = (int64_t)blockIdx.x % (nbt * nbt);
+  int64_t ti, tj;
+  pair_of(y, ti, tj);
+  const int64_t r0 = (blk / nbt) * KB, c0 = (blk % nbt) * KB;
+  double r2[4][4];
+  sqdist_block(Z + ti * b * d, b, r0, Z + tj * b * d, b, c0, d, za, zb, r2);
+  double ell, nu, s2;
+  resolve_hyper(h, ell, nu, s2);
+  const double g = 0.5 / (ell * ell);
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double* Ut = U + y * b * b;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = r0 + ty * 4 + i;
+    if (r >= b) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = c0 + tx * 4 + j;
+      if (c < b) Ut[r * b + c] = g * r2[i][j];
     }
   }
 }
@@ -170,8 +208,19 @@ hipError_t launch_assemble_tiles(const double* Z, int64_t d, HyperArg h, const T
                                  hipStream_t st) {
   if (L.T == 0) return hipSuccess;
   const int64_t nbt = (L.b + KB - 1) / KB;
-  dim3 grid((unsigned)(nbt * nbt), (unsigned)(L.T * (L.T + 1) / 2));
-  hipLaunchKernelGGL(assemble_tiles_kernel, grid, dim3(256), 0, st, Z, d, h, L, K);
+  const int64_t blocks = nbt * nbt * (L.T * (L.T + 1) / 2);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(assemble_tiles_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Z, d, h, L, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_halfdist_tiles(const double* Z, int64_t d, HyperArg h, int64_t b, int64_t T, double* U,
+                                 hipStream_t st) {
+  if (T == 0) return hipSuccess;
+  const int64_t nbt = (b + KB - 1) / KB;
+  const int64_t blocks = nbt * nbt * (T * (T + 1) / 2);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(halfdist_tiles_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Z, d, h, b, U);
   return hipGetLastError();
 }
 

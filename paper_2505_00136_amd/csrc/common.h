@@ -72,7 +72,8 @@ enum { MODE_KC = 0, MODE_MC = 1 };
 enum { TRI_NONE = 0, A_LOWER = 1, A_UPPER = 2, B_LOWER = 4, B_UPPER = 8 };
 // Job flags.
 enum { JOB_LOWER_ONLY = 1,   // skip macro tiles that lie entirely above the diagonal
-       JOB_C_F32 = 2 };      // C and Cin are float32 (else float64)
+       JOB_C_F32 = 2,        // C and Cin are float32 (else float64)
+       JOB_TRACE_ALPHA = 4 };  // gradient trace: this job also subtracts alpha alpha^T
 
 struct GemmSeg {
   const void* A;
@@ -99,12 +100,11 @@ struct GemmJob {
 
 // Arguments of the gradient reduction fused into the K^{-1} product.
 struct TraceArgs {
-  const double* Z;
-  int64_t d;
+  const double* u;       // r^2 / (2 l^2) of every lower tile pair (packed row-major, b x b each)
   const double* alpha;
   HyperArg h;
   int64_t b;
-  double* partial;   // [workgroups][3]
+  double* partial;       // [workgroups][3]
 };
 
 constexpr int GEMM_BM = 128, GEMM_BN = 128, GEMM_BK = 16, GEMM_THREADS = 256;

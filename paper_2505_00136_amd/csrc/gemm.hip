@@ -264,10 +264,21 @@ void gemm_update_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restr
   gemm_tiles_body<T>(jobs, segs, njobs);
 }
 
-// Gradient reduction fused into the K^{-1} = L^{-T} L^{-1} product (see grad_trace in the
-// orchestration): the macro tile of K^{-1} never leaves registers; each element is
-// combined with alpha and with the kernel value and squared distance regenerated from Z,
-// and the workgroup writes its three partial sums to partial[blockIdx.x][0..2].
+// Steps of the triangular inversion L^{-1} of the gradient (same code, own symbol).
+template <typename T>
+__global__ __launch_bounds__(GEMM_THREADS, 2)
+void gemm_trtri_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  gemm_tiles_body<T>(jobs, segs, njobs);
+}
+
+// Gradient reduction fused into the K^{-1} = L^{-T} L^{-1} product: each job is one
+// contribution X_ki^T X_kj of block row k of X = L^{-1} to the K^{-1} tile (i, j) = (aux0,
+// aux1).  The macro tile never leaves registers; each element w (less alpha_r alpha_c when
+// the job carries JOB_TRACE_ALPHA, once per tile) is weighted with the kernel value
+// nu exp(-u) and with 2u = r^2 / l^2, u read from the tile pair's precomputed half scaled
+// squared distances, and the workgroup writes its three partial sums
+// (sum w k 2u, sum w k, sum over the diagonal of w; off-diagonal tile pairs count twice)
+// to partial[blockIdx.x][0..2].
 template <typename T>
 __global__ __launch_bounds__(GEMM_THREADS, 2)
 void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs,
@@ -277,9 +288,6 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
   __shared__ __align__(16) char smem[SMEM_BYTES];
   T (*As)[GEMM_BK][GEMM_BM + LDS_PAD] = reinterpret_cast<T (*)[GEMM_BK][GEMM_BM + LDS_PAD]>(smem);
   T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD] = As + 2;
-  // after the main loop the operand buffers hold the feature blocks of the tile's points
-  double (*zr)[GEMM_BM + LDS_PAD] = reinterpret_cast<double (*)[GEMM_BM + LDS_PAD]>(smem);
-  double (*zc)[GEMM_BN + LDS_PAD] = zr + GEMM_BK;
   __shared__ double red[3][GEMM_THREADS];
   GemmJob job;
   int m0, n0;
@@ -296,38 +304,12 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
     gemm_mainloop<T>(job, segs, m0, n0, acc, As, Bs);
     double ell, nu, s2;
     resolve_hyper(ta.h, ell, nu, s2);
-    const double il2 = 1.0 / (ell * ell);
     const int64_t ti = job.aux0, tj = job.aux1;
     const double wt = (ti == tj) ? 1.0 : 2.0;
-    const int64_t growb = ti * ta.b + m0, gcolb = tj * ta.b + n0;
+    const bool with_alpha = job.flags & JOB_TRACE_ALPHA;
+    const double* __restrict__ U = ta.u + (ti * (ti + 1) / 2 + tj) * ta.b * ta.b;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double r2[4][4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) r2[j][r] = 0.0;
-      for (int64_t f0 = 0; f0 < ta.d; f0 += GEMM_BK) {
-        __syncthreads();
-        for (int e = tid; e < GEMM_BK * GEMM_BM; e += GEMM_THREADS) {
-          const int p = e / GEMM_BK, f = e % GEMM_BK;
-          const int64_t ff = f0 + f;
-          zr[f][p] = (m0 + p < job.M && ff < ta.d) ? ta.Z[(growb + p) * ta.d + ff] : 0.0;
-          zc[f][p] = (n0 + p < job.N && ff < ta.d) ? ta.Z[(gcolb + p) * ta.d + ff] : 0.0;
-        }
-        __syncthreads();
-        for (int f = 0; f < GEMM_BK; ++f) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const double a = zr[f][wm + i * 16 + Op::row(lane, r)];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const double df = a - zc[f][wn + j * 16 + (lane & 15)];
-              r2[j][r] = fma(df, df, r2[j][r]);
-            }
-          }
-        }
-      }
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -335,15 +317,15 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
           const int row = m0 + wm + i * 16 + Op::row(lane, r);
           const int col = n0 + wn + j * 16 + (lane & 15);
           if (row < job.M && col < job.N) {
-            const int64_t gr = ti * ta.b + row, gc = tj * ta.b + col;
-            const double w = (double)acc[i][j][r] - ta.alpha[gr] * ta.alpha[gc];
-            const double kf = nu * exp(-0.5 * r2[j][r] * il2);
-            s_l = fma(wt * w * kf, r2[j][r] * il2, s_l);
+            const double u = U[(int64_t)row * ta.b + col];
+            double w = (double)acc[i][j][r];
+            if (with_alpha) w -= ta.alpha[ti * ta.b + row] * ta.alpha[tj * ta.b + col];
+            const double kf = nu * exp(-u);
+            s_l = fma(wt * w * kf, 2.0 * u, s_l);
             s_nu = fma(wt * w, kf, s_nu);
-            if (gr == gc) s_s += w;
+            if (ti == tj && row == col) s_s += w;
           }
         }
-    }
   }
   red[0][tid] = s_l;
   red[1][tid] = s_nu;
@@ -374,6 +356,14 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
     hipLaunchKernelGGL(gemm_widen_kernel, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
     return hipGetLastError();
   }
+  if (kind == GEMM_KIND_TRTRI) {
+    if (prec_f32)
+      hipLaunchKernelGGL(gemm_trtri_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+    else
+      hipLaunchKernelGGL(gemm_trtri_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+    return hipGetLastError();
+  }
+  if (kind == GEMM_KIND_TRACE) return hipErrorInvalidValue;   // launched by launch_gemm_trace
   if (kind == GEMM_KIND_UPDATE) {
     if (prec_f32)
       hipLaunchKernelGGL(gemm_update_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);

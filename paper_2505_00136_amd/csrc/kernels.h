@@ -9,7 +9,9 @@ namespace gpr {
 // gemm.hip / gemm_bf16.hip
 // GENERIC/UPDATE: operands and products in the launch precision; WIDEN: float32 operands,
 // float64 products; BF16X3/X6: split-bfloat16 products of bfloat16 planes.
-enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_KIND_BF16X6 = 3, GEMM_KIND_WIDEN = 4 };
+enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_KIND_BF16X6 = 3, GEMM_KIND_WIDEN = 4,
+       GEMM_KIND_TRTRI = 5,    // triangular-inverse steps of the gradient (own kernel symbol)
+       GEMM_KIND_TRACE = 6 };  // K^{-1} products fused with the gradient reduction (launch_gemm_trace)
 hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind,
                        hipStream_t st);
 
@@ -37,6 +39,9 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 hipError_t launch_assemble_tiles(const double* Z, int64_t d, HyperArg h, const TileLayout& L, void* K,
                                  hipStream_t st);
 // Dense covariance block out[r*ld + c] = k(A_r, B_c) (+ s2 where r == c when add_diag), float64 or float32.
+// u = r^2 / (2 l^2) of every lower tile pair (T (T+1)/2 float64 b x b tiles, packed row-major)
+hipError_t launch_halfdist_tiles(const double* Z, int64_t d, HyperArg h, int64_t b, int64_t T, double* U,
+                                 hipStream_t st);
 hipError_t launch_assemble_dense(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
                                  HyperArg h, int add_diag, void* out, int64_t ld, int out_f32,
                                  hipStream_t st);

@@ -15,14 +15,15 @@
 
 namespace gpr {
 
-// Optional event timing of the trailing-update launches (a profiling hook of the C-ABI).
+// Optional event timing of the dominant tile-GEMM launches (a profiling hook of the C-ABI).
 struct TimingLog {
   std::mutex mu;
   bool on = false;
   struct Rec {
     hipEvent_t a, b;
     double flops;
-    int kind;   // 0: float64 update, 1: float32 update, 2: bf16x3 update, 3: bf16x6 update
+    int kind;   // timing kind: 0/1 float64/float32 update, 2/3 bf16x3/bf16x6 update,
+                // 4/5 float64/float32 inversion step, 6/7 float64/float32 gradient trace
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -51,6 +52,10 @@ struct Program {
   int job0 = 0, nwg = 0, f32 = 0, kind = 0;
   double kind_flops = 0.0;
   bool cur_valid = false;
+  // gradient-trace launches: arguments, and running count of their workgroups (each writes
+  // three partial sums at partial + 3 * (trace_wg + its block index)); trace_cap bounds it
+  const TraceArgs* trace = nullptr;
+  int64_t trace_wg = 0, trace_cap = 0;
 
   hipStream_t stream() const { return st; }
 
@@ -116,7 +121,8 @@ struct Program {
     gemm_flops_wg += nwg;
     hipEvent_t ea = nullptr, eb = nullptr;
     bool timed = false;
-    if (kind == GEMM_KIND_UPDATE || kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6) {
+    if (kind == GEMM_KIND_UPDATE || kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6 ||
+        kind == GEMM_KIND_TRTRI || kind == GEMM_KIND_TRACE) {
       std::lock_guard<std::mutex> lk(g_timing.mu);
       if (g_timing.on) {
         ea = g_timing.get();
@@ -125,12 +131,27 @@ struct Program {
       }
     }
     hipStream_t sx = stream();
+    if (kind == GEMM_KIND_TRACE && (!trace || trace_wg + nwg > trace_cap)) {
+      err = hipErrorInvalidValue;
+      return;
+    }
     if (timed) (void)hipEventRecord(ea, sx);
-    err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, sx);
+    if (kind == GEMM_KIND_TRACE) {
+      TraceArgs ta = *trace;
+      ta.partial += 3 * trace_wg;
+      err = launch_gemm_trace(f32, djobs + job0, dsegs, nj, nwg, ta, sx);
+      trace_wg += nwg;
+    } else {
+      err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, sx);
+    }
     if (timed) {
       (void)hipEventRecord(eb, sx);
       std::lock_guard<std::mutex> lk(g_timing.mu);
-      const int tk = kind == GEMM_KIND_BF16X3 ? 2 : kind == GEMM_KIND_BF16X6 ? 3 : (f32 ? 1 : 0);
+      int tk = f32 ? 1 : 0;
+      if (kind == GEMM_KIND_BF16X3) tk = 2;
+      else if (kind == GEMM_KIND_BF16X6) tk = 3;
+      else if (kind == GEMM_KIND_TRTRI) tk = f32 ? 5 : 4;
+      else if (kind == GEMM_KIND_TRACE) tk = f32 ? 7 : 6;
       g_timing.recs.push_back({ea, eb, kind_flops, tk});
     }
   }
