@@ -47,6 +47,15 @@ GPR_DEV void seg_krange(const GemmSeg& s, int m0, int n0, int& kb, int& ke) {
   kb = (kb / GEMM_BK) * GEMM_BK;
 }
 
+// Operand loads go through global-address-space pointers: generic (flat) loads would
+// also count against the LDS wait counter, so waiting for the current chunk's LDS
+// fragments would wait for the next chunk's prefetch as well.
+template <typename V>
+GPR_DEV V load_global(const void* p) {
+  typedef __attribute__((address_space(1))) const V gV;
+  return *(gV*)(p);
+}
+
 // Loads this thread's share of a 128 x 16 operand chunk into registers (zero outside
 // [0,lim) x [k0,kend)).  When the whole chunk is in range and the rows are 16-byte
 // aligned (a uniform test), the loads are unguarded 16-byte vector loads; otherwise
@@ -64,7 +73,7 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
         const int row = base + (tid >> 3) + 32 * p;
         const T* q = P + (int64_t)row * ld + kk;
         typedef T v2 __attribute__((ext_vector_type(2)));
-        const v2 v = *reinterpret_cast<const v2*>(q);
+        const v2 v = load_global<v2>(q);
         r[2 * p] = v[0];
         r[2 * p + 1] = v[1];
       }
@@ -75,8 +84,8 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
       const int row = base + (tid >> 3) + 32 * p;
       const bool rok = row < lim;
       const T* q = P + (int64_t)row * ld + kk;
-      r[2 * p] = (rok && kk < kend) ? q[0] : T(0);
-      r[2 * p + 1] = (rok && kk + 1 < kend) ? q[1] : T(0);
+      r[2 * p] = (rok && kk < kend) ? load_global<T>(q) : T(0);
+      r[2 * p + 1] = (rok && kk + 1 < kend) ? load_global<T>(q + 1) : T(0);
     }
   } else {
     const int k = k0 + (tid >> 4);
@@ -86,7 +95,7 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
       typedef T vv __attribute__((ext_vector_type(VEC)));
 #pragma unroll
       for (int e = 0; e < 8; e += VEC) {
-        const vv v = *reinterpret_cast<const vv*>(q + e);
+        const vv v = load_global<vv>(q + e);
 #pragma unroll
         for (int x = 0; x < VEC; ++x) r[e + x] = v[x];
       }
@@ -94,7 +103,7 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
     }
     const bool kok = k < kend;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = (kok && r0 + e < lim) ? q[e] : T(0);
+    for (int e = 0; e < 8; ++e) r[e] = (kok && r0 + e < lim) ? load_global<T>(q + e) : T(0);
   }
 }
 
@@ -132,10 +141,12 @@ GPR_DEV bool locate_job(const GemmJob* __restrict__ jobs, int njobs, GemmJob& jo
   return !((job.flags & JOB_LOWER_ONLY) && (m0 + GEMM_BM - 1 < n0));
 }
 
-// acc += sum over the job's segments of the 128 x 128 macro tile at (m0, n0); operands are
-// stored as TL and multiplied as T (float operands may be widened to float64 products).
-template <typename T, typename TL = T>
-GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
+// Guarded main loop (any shapes, alignments and operand modes): acc += sum over the job's
+// segments of the 128 x 128 macro tile at (m0, n0).  The next chunk, possibly the first of
+// the next segment, is loaded while the current one is multiplied; each load takes the
+// vector path when its chunk lies inside an aligned operand.
+template <typename T, typename TL>
+GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
                            typename MfmaOp<T>::acc_t (&acc)[4][4], T (*As)[GEMM_BK][GEMM_BM + LDS_PAD],
                            T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
   typedef MfmaOp<T> Op;
@@ -189,6 +200,7 @@ GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs,
         for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
     }
     if (!more) break;
+    __builtin_amdgcn_sched_barrier(0);
     store_chunk<T, TL>(As[buf ^ 1], nmodeA, tid, ra);
     store_chunk<T, TL>(Bs[buf ^ 1], nmodeB, tid, rb);
     __syncthreads();
@@ -199,7 +211,107 @@ GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs,
   }
 }
 
-template <typename T, typename TL = T>
+// Unguarded chunk load for a macro tile that lies inside the operand with 16-byte aligned
+// rows (the caller has checked): KC, 2 consecutive k of 4 rows per thread; MC, 8
+// consecutive rows of one k per thread.
+template <typename TL, int MODE>
+GPR_DEV void load_chunk_full(const TL* __restrict__ P, int64_t ld, int base, int k0, int tid, TL (&r)[8]) {
+  if (MODE == MODE_KC) {
+    typedef TL v2 __attribute__((ext_vector_type(2)));
+    const int kk = k0 + (tid & 7) * 2;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const v2 v = load_global<v2>(P + (int64_t)(base + (tid >> 3) + 32 * p) * ld + kk);
+      r[2 * p] = v[0];
+      r[2 * p + 1] = v[1];
+    }
+  } else {
+    constexpr int VEC = 16 / sizeof(TL);
+    typedef TL vv __attribute__((ext_vector_type(VEC)));
+    const TL* q = P + (int64_t)(k0 + (tid >> 4)) * ld + base + (tid & 15) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; e += VEC) {
+      const vv v = load_global<vv>(q + e);
+#pragma unroll
+      for (int x = 0; x < VEC; ++x) r[e + x] = v[x];
+    }
+  }
+}
+
+template <typename T>
+GPR_DEV void mma_chunk(const T (*As)[GEMM_BM + LDS_PAD], const T (*Bs)[GEMM_BN + LDS_PAD], int lane, int wm, int wn,
+                       typename MfmaOp<T>::acc_t (&acc)[4][4]) {
+  typedef MfmaOp<T> Op;
+#pragma unroll
+  for (int kq = 0; kq < GEMM_BK / 4; ++kq) {
+    const int kr = kq * 4 + (lane >> 4);
+    T a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+  }
+}
+
+// One segment's k range [kb, ke) (whole chunks) of a macro tile inside both operands:
+// straight-line loads and stores for fixed modes, LDS double buffer, one barrier per chunk.
+// Starts with a barrier, so the previous segment's last chunk may still be in LDS.
+template <typename T, typename TL, int MA, int MB>
+GPR_DEV void seg_full(const GemmSeg& s, int m0, int n0, int kb, int ke, typename MfmaOp<T>::acc_t (&acc)[4][4],
+                      T (*As)[GEMM_BK][GEMM_BM + LDS_PAD], T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const TL* __restrict__ A = (const TL*)s.A;
+  const TL* __restrict__ B = (const TL*)s.B;
+  TL ra[8], rb[8];
+  load_chunk_full<TL, MA>(A, s.lda, m0, kb, tid, ra);
+  load_chunk_full<TL, MB>(B, s.ldb, n0, kb, tid, rb);
+  __syncthreads();
+  store_chunk<T, TL>(As[0], MA, tid, ra);
+  store_chunk<T, TL>(Bs[0], MB, tid, rb);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb; k0 + GEMM_BK < ke; k0 += GEMM_BK) {
+    load_chunk_full<TL, MA>(A, s.lda, m0, k0 + GEMM_BK, tid, ra);
+    load_chunk_full<TL, MB>(B, s.ldb, n0, k0 + GEMM_BK, tid, rb);
+    mma_chunk<T>(As[buf], Bs[buf], lane, wm, wn, acc);
+    // keep the stores of the next chunk (which wait for its global loads) after the products
+    __builtin_amdgcn_sched_barrier(0);
+    store_chunk<T, TL>(As[buf ^ 1], MA, tid, ra);
+    store_chunk<T, TL>(Bs[buf ^ 1], MB, tid, rb);
+    __syncthreads();
+    buf ^= 1;
+  }
+  mma_chunk<T>(As[buf], Bs[buf], lane, wm, wn, acc);
+}
+
+// Operand-mode specialisations of the main loop.  SPEC_GUARDED runs the guarded loop; the
+// others run the straight-line loop of one operand-mode pair and are chosen by the host
+// only for launches whose jobs all cover whole macro tiles (M, N multiples of 128), whose
+// segments all have K a multiple of 16, 16-byte aligned rows and that mode pair.
+enum { SPEC_GUARDED = -1, SPEC_KK = 0, SPEC_KM = 1, SPEC_MM = 3 };
+
+template <typename T, typename TL, int SPEC>
+GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
+                           typename MfmaOp<T>::acc_t (&acc)[4][4], T (*As)[GEMM_BK][GEMM_BM + LDS_PAD],
+                           T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
+  if constexpr (SPEC == SPEC_GUARDED) {
+    gemm_mainloop_generic<T, TL>(job, segs, m0, n0, acc, As, Bs);
+  } else {
+    for (int cs = job.seg0; cs < job.seg0 + job.nseg; ++cs) {
+      const GemmSeg& s = segs[cs];
+      int kb, ke;
+      seg_krange<T>(s, m0, n0, kb, ke);
+      if (kb < ke) seg_full<T, TL, (SPEC >> 1), (SPEC & 1)>(s, m0, n0, kb, ke, acc, As, Bs);
+    }
+  }
+}
+
+template <typename T, typename TL, int SPEC>
 GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
   typedef MfmaOp<T> Op;
   typedef typename Op::acc_t acc_t;
@@ -214,7 +326,7 @@ GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-  gemm_mainloop<T, TL>(job, segs, m0, n0, acc, As, Bs);
+  gemm_mainloop<T, TL, SPEC>(job, segs, m0, n0, acc, As, Bs);
 
   // epilogue: C = alpha * acc + beta * Cin
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -243,32 +355,33 @@ GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __
 }
 
 // General tile products (in-tile factorisation, TRSM, solves, inversion).
-template <typename T>
+template <typename T, int SPEC>
 __global__ __launch_bounds__(GEMM_THREADS, 2)
 void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<T>(jobs, segs, njobs);
+  gemm_tiles_body<T, T, SPEC>(jobs, segs, njobs);
 }
 
 // float32-stored operands multiplied in float64 (exact products): the diagonal-tile
 // SYRK of the mixed-precision factorisations.
+template <int SPEC>
 __global__ __launch_bounds__(GEMM_THREADS, 2)
 void gemm_widen_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<double, float>(jobs, segs, njobs);
+  gemm_tiles_body<double, float, SPEC>(jobs, segs, njobs);
 }
 
 // The trailing SYRK/GEMM update of a factorisation step (same code, its own symbol so
 // that profiles and timings single it out).
-template <typename T>
+template <typename T, int SPEC>
 __global__ __launch_bounds__(GEMM_THREADS, 2)
 void gemm_update_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<T>(jobs, segs, njobs);
+  gemm_tiles_body<T, T, SPEC>(jobs, segs, njobs);
 }
 
 // Steps of the triangular inversion L^{-1} of the gradient (same code, own symbol).
-template <typename T>
+template <typename T, int SPEC>
 __global__ __launch_bounds__(GEMM_THREADS, 2)
 void gemm_trtri_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<T>(jobs, segs, njobs);
+  gemm_tiles_body<T, T, SPEC>(jobs, segs, njobs);
 }
 
 // Gradient reduction fused into the K^{-1} = L^{-T} L^{-1} product: each job is one
@@ -279,7 +392,7 @@ void gemm_trtri_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 // squared distances, and the workgroup writes its three partial sums
 // (sum w k 2u, sum w k, sum over the diagonal of w; off-diagonal tile pairs count twice)
 // to partial[blockIdx.x][0..2].
-template <typename T>
+template <typename T, int SPEC>
 __global__ __launch_bounds__(GEMM_THREADS, 2)
 void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs,
                        TraceArgs ta) {
@@ -301,7 +414,7 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    gemm_mainloop<T>(job, segs, m0, n0, acc, As, Bs);
+    gemm_mainloop<T, T, SPEC>(job, segs, m0, n0, acc, As, Bs);
     double ell, nu, s2;
     resolve_hyper(ta.h, ell, nu, s2);
     const int64_t ti = job.aux0, tj = job.aux1;
@@ -347,47 +460,84 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
   }
 }
 
-hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind,
+// Host: the specialised main loop a launch may use (SPEC_GUARDED if any job or segment
+// needs guards or the segments mix operand modes).  esize: bytes per stored operand element.
+int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int esize) {
+  int spec = -2;
+  auto aligned = [](const void* p, int64_t ld, int es) {
+    return (((uintptr_t)p) & 15) == 0 && (ld * es) % 16 == 0;
+  };
+  for (int j = 0; j < njobs; ++j) {
+    const GemmJob& J = jobs[j];
+    if (J.M % GEMM_BM != 0 || J.N % GEMM_BN != 0) return SPEC_GUARDED;
+    for (int q = J.seg0; q < J.seg0 + J.nseg; ++q) {
+      const GemmSeg& S = segs[q];
+      if (S.K % GEMM_BK != 0 || !aligned(S.A, S.lda, esize) || !aligned(S.B, S.ldb, esize)) return SPEC_GUARDED;
+      const int sp = S.modeA * 2 + S.modeB;
+      if (spec == -2) spec = sp;
+      else if (spec != sp) return SPEC_GUARDED;
+    }
+  }
+  return spec < 0 ? SPEC_GUARDED : spec;
+}
+
+#define GPR_GEMM_LAUNCH(kern) \
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs)
+
+template <typename T>
+hipError_t launch_tiles_t(const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int spec, hipStream_t st) {
+  if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_tiles_kernel<T, SPEC_KK>));
+  else if (spec == SPEC_KM) GPR_GEMM_LAUNCH((gemm_tiles_kernel<T, SPEC_KM>));
+  else if (spec == SPEC_MM) GPR_GEMM_LAUNCH((gemm_tiles_kernel<T, SPEC_MM>));
+  else GPR_GEMM_LAUNCH((gemm_tiles_kernel<T, SPEC_GUARDED>));
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind, int spec,
                        hipStream_t st) {
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
   if (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
     return launch_gemm_bf16(kind == GEMM_KIND_BF16X6 ? 6 : 3, jobs, segs, njobs, nwg, st);
-  if (kind == GEMM_KIND_WIDEN) {
-    hipLaunchKernelGGL(gemm_widen_kernel, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
-    return hipGetLastError();
-  }
-  if (kind == GEMM_KIND_TRTRI) {
-    if (prec_f32)
-      hipLaunchKernelGGL(gemm_trtri_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
-    else
-      hipLaunchKernelGGL(gemm_trtri_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
-    return hipGetLastError();
-  }
   if (kind == GEMM_KIND_TRACE) return hipErrorInvalidValue;   // launched by launch_gemm_trace
-  if (kind == GEMM_KIND_UPDATE) {
-    if (prec_f32)
-      hipLaunchKernelGGL(gemm_update_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
-    else
-      hipLaunchKernelGGL(gemm_update_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+  if (kind == GEMM_KIND_WIDEN) {
+    if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_KK>));
+    else GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_GUARDED>));
+  } else if (kind == GEMM_KIND_TRTRI) {
+    if (prec_f32) {
+      if (spec == SPEC_KM) GPR_GEMM_LAUNCH((gemm_trtri_kernel<float, SPEC_KM>));
+      else GPR_GEMM_LAUNCH((gemm_trtri_kernel<float, SPEC_GUARDED>));
+    } else {
+      if (spec == SPEC_KM) GPR_GEMM_LAUNCH((gemm_trtri_kernel<double, SPEC_KM>));
+      else GPR_GEMM_LAUNCH((gemm_trtri_kernel<double, SPEC_GUARDED>));
+    }
+  } else if (kind == GEMM_KIND_UPDATE) {
+    if (prec_f32) {
+      if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_update_kernel<float, SPEC_KK>));
+      else GPR_GEMM_LAUNCH((gemm_update_kernel<float, SPEC_GUARDED>));
+    } else {
+      if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_update_kernel<double, SPEC_KK>));
+      else GPR_GEMM_LAUNCH((gemm_update_kernel<double, SPEC_GUARDED>));
+    }
   } else {
-    if (prec_f32)
-      hipLaunchKernelGGL(gemm_tiles_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
-    else
-      hipLaunchKernelGGL(gemm_tiles_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs);
+    return prec_f32 ? launch_tiles_t<float>(jobs, segs, njobs, nwg, spec, st)
+                    : launch_tiles_t<double>(jobs, segs, njobs, nwg, spec, st);
   }
   return hipGetLastError();
 }
+#undef GPR_GEMM_LAUNCH
 
-}  // namespace gpr
-
-namespace gpr {
-hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int spec,
                              const TraceArgs& ta, hipStream_t st) {
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
-  if (prec_f32)
-    hipLaunchKernelGGL(gemm_trace_kernel<float>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs, ta);
-  else
-    hipLaunchKernelGGL(gemm_trace_kernel<double>, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs, ta);
+  const dim3 g(nwg), blk(GEMM_THREADS);
+  if (prec_f32) {
+    if (spec == SPEC_MM) hipLaunchKernelGGL((gemm_trace_kernel<float, SPEC_MM>), g, blk, 0, st, jobs, segs, njobs, ta);
+    else hipLaunchKernelGGL((gemm_trace_kernel<float, SPEC_GUARDED>), g, blk, 0, st, jobs, segs, njobs, ta);
+  } else {
+    if (spec == SPEC_MM) hipLaunchKernelGGL((gemm_trace_kernel<double, SPEC_MM>), g, blk, 0, st, jobs, segs, njobs, ta);
+    else hipLaunchKernelGGL((gemm_trace_kernel<double, SPEC_GUARDED>), g, blk, 0, st, jobs, segs, njobs, ta);
+  }
   return hipGetLastError();
 }
+
 }  // namespace gpr

@@ -12,11 +12,15 @@ namespace gpr {
 enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_KIND_BF16X6 = 3, GEMM_KIND_WIDEN = 4,
        GEMM_KIND_TRTRI = 5,    // triangular-inverse steps of the gradient (own kernel symbol)
        GEMM_KIND_TRACE = 6 };  // K^{-1} products fused with the gradient reduction (launch_gemm_trace)
-hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind,
+// spec: main-loop specialisation from gemm_launch_spec (host tables of the launch)
+hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind, int spec,
                        hipStream_t st);
-
-hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int spec,
                              const TraceArgs& ta, hipStream_t st);
+// Straight-line main loop of one operand-mode pair (0: KC/KC, 1: KC/MC, 3: MC/MC) when every
+// job covers whole 128 x 128 macro tiles and every segment has K % 16 == 0, 16-byte aligned
+// rows and that pair; -1 (guarded loop) otherwise.  esize: bytes per stored operand element.
+int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int esize);
 
 // gemm_bf16.hip: trailing update from split-bfloat16 planes (nprod 3 or 6); KC operands only
 hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, hipStream_t st);

@@ -135,14 +135,17 @@ struct Program {
       err = hipErrorInvalidValue;
       return;
     }
+    const int esize = (f32 || kind == GEMM_KIND_WIDEN) ? 4 : 8;
+    const int spec = (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
+                         ? -1 : gemm_launch_spec(jobs.data() + job0, nj, segs.data(), esize);
     if (timed) (void)hipEventRecord(ea, sx);
     if (kind == GEMM_KIND_TRACE) {
       TraceArgs ta = *trace;
       ta.partial += 3 * trace_wg;
-      err = launch_gemm_trace(f32, djobs + job0, dsegs, nj, nwg, ta, sx);
+      err = launch_gemm_trace(f32, djobs + job0, dsegs, nj, nwg, spec, ta, sx);
       trace_wg += nwg;
     } else {
-      err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, sx);
+      err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, spec, sx);
     }
     if (timed) {
       (void)hipEventRecord(eb, sx);
