@@ -119,6 +119,23 @@ GPR_DEV int xcd_remap(int bid, int nblocks) {
   return start + local;
 }
 
+// Macro tile (m0, n0) of the job's t-th workgroup.  Tiles are visited in 8 x 8 blocks
+// (row-major inside and between blocks) when the job's tile grid allows: consecutive
+// workgroups land on one XCD (xcd_remap), and its ~64 resident workgroups then form a
+// square patch that shares 8 A and 8 B row blocks through the XCD's L2 instead of a
+// 4 x 16 strip sharing 4 and 16.
+GPR_DEV void job_tile(const GemmJob& job, int t, int& m0, int& n0) {
+  const int tn = job.tiles_n, tm = (job.M + GEMM_BM - 1) / GEMM_BM;
+  if ((tn & 7) == 0 && (tm & 7) == 0) {
+    const int sb = t >> 6, w = t & 63, sbn = tn >> 3;
+    m0 = ((sb / sbn) * 8 + (w >> 3)) * GEMM_BM;
+    n0 = ((sb % sbn) * 8 + (w & 7)) * GEMM_BN;
+  } else {
+    m0 = (t / tn) * GEMM_BM;
+    n0 = (t % tn) * GEMM_BN;
+  }
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace gpr

@@ -135,9 +135,7 @@ GPR_DEV bool locate_job(const GemmJob* __restrict__ jobs, int njobs, GemmJob& jo
     if (jobs[mid].wg_begin <= bid) lo = mid; else hi = mid - 1;
   }
   job = jobs[lo];
-  const int t = bid - job.wg_begin;
-  m0 = (t / job.tiles_n) * GEMM_BM;
-  n0 = (t % job.tiles_n) * GEMM_BN;
+  job_tile(job, bid - job.wg_begin, m0, n0);
   return !((job.flags & JOB_LOWER_ONLY) && (m0 + GEMM_BM - 1 < n0));
 }
 

@@ -93,9 +93,8 @@ void gemm_bf16x_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
     if (jobs[mid].wg_begin <= bid) lo = mid; else hi = mid - 1;
   }
   const GemmJob job = jobs[lo];
-  const int t = bid - job.wg_begin;
-  const int m0 = (t / job.tiles_n) * GEMM_BM;
-  const int n0 = (t % job.tiles_n) * GEMM_BN;
+  int m0, n0;
+  job_tile(job, bid - job.wg_begin, m0, n0);
   if ((job.flags & JOB_LOWER_ONLY) && (m0 + GEMM_BM - 1 < n0)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;

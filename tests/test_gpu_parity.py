@@ -137,6 +137,25 @@ def test_tilings_and_ragged_sizes(lib, n, tile, D):
     assert _rel(var, oracle.predict_var(Z, Zs, h, L)) < 1e-10
 
 
+@pytest.mark.parametrize("n,tile", [(2048, 1024), (3072, 1024)])
+def test_large_tile_parity(lib, n, tile):
+    """Tiles of 1024: every job's 128 x 128 macro-tile grid is a multiple of 8 in both
+    directions, so the GEMMs take the 8 x 8 block order of their workgroups."""
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=n, n_test=64, D=16, seed=n))
+    h = Hyper(4.0, 1.0, 0.01)
+    L, a, f = oracle.fit(ds.Z, ds.y, h)
+    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, m=64)
+    assert abs(g["nlml"] - f) / abs(f) < 1e-10
+    assert _rel(g["alpha"].cpu().numpy(), a) < 1e-10
+    mean, var = _gpu_predict(lib, g, ds.Zs, h)
+    assert _rel(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a)) < 1e-10
+    assert _rel(var, oracle.predict_var(ds.Z, ds.Zs, h, L)) < 1e-10
+    grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    lib.gpr_nlml_grad(g["Z"], g["n"], g["d"], h, g["K"], tile, "fp64", g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
+    go = oracle.nlml_grad(ds.Z, h, L, a)
+    np.testing.assert_allclose(grad.cpu().numpy(), go, rtol=1e-9, atol=1e-9 * np.max(np.abs(go)))
+
+
 def test_tiling_invariance_bitwise_determinism(lib):
     rng = np.random.default_rng(3)
     n, D = 768, 8
