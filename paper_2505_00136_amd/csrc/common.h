@@ -107,7 +107,7 @@ struct TraceArgs {
   double* partial;       // [workgroups][3]
 };
 
-constexpr int GEMM_BM = 128, GEMM_BN = 128, GEMM_BK = 16, GEMM_THREADS = 256;
+constexpr int GEMM_BM = 128, GEMM_BN = 128, GEMM_THREADS = 256;   // macro tile, workgroup size
 
 // Workgroup w is dispatched to XCD w % 8; remap so that every XCD gets a contiguous
 // range of logical workgroups (neighbouring macro tiles share operands in that XCD's L2).

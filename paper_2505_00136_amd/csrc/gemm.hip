@@ -32,9 +32,23 @@ template <> struct MfmaOp<float> {
   static GPR_DEV int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int LDS_PAD = 4;
-// double-buffered A and B chunks of the widest element type (float64)
-constexpr int SMEM_BYTES = 2 * 2 * GEMM_BK * (GEMM_BM + LDS_PAD) * 8;
+// Per compute type T: K depth of an LDS chunk, elements each thread stages per operand
+// and chunk, and LDS row pitch.  16-deep chunks for both float64 and float32 (measured:
+// 32-deep float32 chunks, padded float32 pitches and three or four workgroups per CU were
+// all slower than two workgroups per CU with this configuration).
+template <typename T>
+struct Chunk {
+  static constexpr int BK = 16;
+  static constexpr int E = BK * GEMM_BM / GEMM_THREADS;   // 8
+  static constexpr int KPT = E / 4;                        // KC: consecutive k per thread and row
+  static constexpr int TPR = GEMM_BM / E;                  // MC: threads per k row
+  static constexpr int LD = GEMM_BM + 4;                   // LDS row pitch (elements)
+  static constexpr int SMEM = 2 * 2 * BK * LD * (int)sizeof(T);   // A and B, double-buffered
+};
+template <typename T>
+using LdsBuf = T (*)[Chunk<T>::BK][Chunk<T>::LD];   // [buffer][k][row]
+template <typename T>
+using LdsChunk = T (*)[Chunk<T>::LD];               // [k][row]
 
 template <typename T>
 GPR_DEV void seg_krange(const GemmSeg& s, int m0, int n0, int& kb, int& ke) {
@@ -44,7 +58,7 @@ GPR_DEV void seg_krange(const GemmSeg& s, int m0, int n0, int& kb, int& ke) {
   if (s.tri & B_LOWER) ke = min(ke, n0 + GEMM_BN);
   if (s.tri & A_UPPER) kb = max(kb, m0);
   if (s.tri & B_UPPER) kb = max(kb, n0);
-  kb = (kb / GEMM_BK) * GEMM_BK;
+  kb = (kb / Chunk<T>::BK) * Chunk<T>::BK;
 }
 
 // Operand loads go through global-address-space pointers: generic (flat) loads would
@@ -56,26 +70,26 @@ GPR_DEV V load_global(const void* p) {
   return *(gV*)(p);
 }
 
-// Loads this thread's share of a 128 x 16 operand chunk into registers (zero outside
-// [0,lim) x [k0,kend)).  When the whole chunk is in range and the rows are 16-byte
-// aligned (a uniform test), the loads are unguarded 16-byte vector loads; otherwise
-// every element is guarded.
-template <typename T>
-GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base, int lim,
-                        int k0, int kend, int tid, T (&r)[8]) {
-  constexpr int VEC = 16 / sizeof(T);   // elements per 16-byte load
-  const bool aligned = ((((uintptr_t)P) & 15) == 0) && (ld % VEC == 0);
+// Loads this thread's share of a 128 x BK operand chunk (stored as TL) into registers,
+// zero outside [0,lim) x [k0,kend).  KC: KPT consecutive k of 4 rows; MC: E consecutive
+// rows of one k.  When the whole chunk is in range and the rows are 16-byte aligned (a
+// uniform test) the loads are unguarded vector loads; otherwise every element is guarded.
+template <typename T, typename TL>
+GPR_DEV void load_chunk(const TL* __restrict__ P, int64_t ld, int mode, int base, int lim, int k0, int kend,
+                        int tid, TL (&r)[Chunk<T>::E]) {
+  typedef Chunk<T> C;
+  constexpr int VEC = 16 / sizeof(TL);
+  const bool full = ((((uintptr_t)P) & 15) == 0) && ((ld * (int64_t)sizeof(TL)) % 16 == 0) &&
+                    base + GEMM_BM <= lim && k0 + C::BK <= kend;
   if (mode == MODE_KC) {
-    const int kk = k0 + (tid & 7) * 2;
-    if (aligned && base + GEMM_BM <= lim && k0 + GEMM_BK <= kend && (VEC == 2)) {
+    const int kk = k0 + (tid & 7) * C::KPT;
+    if (full) {
+      typedef TL vk __attribute__((ext_vector_type(C::KPT)));
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const int row = base + (tid >> 3) + 32 * p;
-        const T* q = P + (int64_t)row * ld + kk;
-        typedef T v2 __attribute__((ext_vector_type(2)));
-        const v2 v = load_global<v2>(q);
-        r[2 * p] = v[0];
-        r[2 * p + 1] = v[1];
+        const vk v = load_global<vk>(P + (int64_t)(base + (tid >> 3) + 32 * p) * ld + kk);
+#pragma unroll
+        for (int e = 0; e < C::KPT; ++e) r[p * C::KPT + e] = v[e];
       }
       return;
     }
@@ -83,18 +97,18 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
     for (int p = 0; p < 4; ++p) {
       const int row = base + (tid >> 3) + 32 * p;
       const bool rok = row < lim;
-      const T* q = P + (int64_t)row * ld + kk;
-      r[2 * p] = (rok && kk < kend) ? load_global<T>(q) : T(0);
-      r[2 * p + 1] = (rok && kk + 1 < kend) ? load_global<T>(q + 1) : T(0);
+      const TL* q = P + (int64_t)row * ld + kk;
+#pragma unroll
+      for (int e = 0; e < C::KPT; ++e) r[p * C::KPT + e] = (rok && kk + e < kend) ? load_global<TL>(q + e) : TL(0);
     }
   } else {
-    const int k = k0 + (tid >> 4);
-    const int r0 = base + (tid & 15) * 8;
-    const T* q = P + (int64_t)k * ld + r0;
-    if (aligned && base + GEMM_BM <= lim && k0 + GEMM_BK <= kend) {
-      typedef T vv __attribute__((ext_vector_type(VEC)));
+    const int k = k0 + tid / C::TPR;
+    const int r0 = base + (tid % C::TPR) * C::E;
+    const TL* q = P + (int64_t)k * ld + r0;
+    if (full) {
+      typedef TL vv __attribute__((ext_vector_type(VEC)));
 #pragma unroll
-      for (int e = 0; e < 8; e += VEC) {
+      for (int e = 0; e < C::E; e += VEC) {
         const vv v = load_global<vv>(q + e);
 #pragma unroll
         for (int x = 0; x < VEC; ++x) r[e + x] = v[x];
@@ -103,25 +117,46 @@ GPR_DEV void load_chunk(const T* __restrict__ P, int64_t ld, int mode, int base,
     }
     const bool kok = k < kend;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = (kok && r0 + e < lim) ? load_global<T>(q + e) : T(0);
+    for (int e = 0; e < C::E; ++e) r[e] = (kok && r0 + e < lim) ? load_global<TL>(q + e) : TL(0);
   }
 }
 
 template <typename T, typename TL>
-GPR_DEV void store_chunk(T (*S)[GEMM_BM + LDS_PAD], int mode, int tid, const TL (&r)[8]) {
+GPR_DEV void store_chunk(LdsChunk<T> S, int mode, int tid, const TL (&r)[Chunk<T>::E]) {
+  typedef Chunk<T> C;
   if (mode == MODE_KC) {
-    const int kk = (tid & 7) * 2;
+    const int kk = (tid & 7) * C::KPT;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int row = (tid >> 3) + 32 * p;
-      S[kk][row] = (T)r[2 * p];
-      S[kk + 1][row] = (T)r[2 * p + 1];
+#pragma unroll
+      for (int e = 0; e < C::KPT; ++e) S[kk + e][row] = (T)r[p * C::KPT + e];
     }
   } else {
-    const int k = tid >> 4;
-    const int r0 = (tid & 15) * 8;
+    const int k = tid / C::TPR;
+    const int r0 = (tid % C::TPR) * C::E;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) S[k][r0 + e] = (T)r[e];
+    for (int e = 0; e < C::E; ++e) S[k][r0 + e] = (T)r[e];
+  }
+}
+
+// acc += the products of one LDS chunk: each wave's 64 x 64 quadrant as 4 x 4 MFMA tiles.
+template <typename T>
+GPR_DEV void mma_chunk(LdsChunk<T> As, LdsChunk<T> Bs, int lane, int wm, int wn,
+                       typename MfmaOp<T>::acc_t (&acc)[4][4]) {
+  typedef MfmaOp<T> Op;
+#pragma unroll
+  for (int kq = 0; kq < Chunk<T>::BK / 4; ++kq) {
+    const int kr = kq * 4 + (lane >> 4);
+    T a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
   }
 }
 
@@ -145,9 +180,8 @@ GPR_DEV bool locate_job(const GemmJob* __restrict__ jobs, int njobs, GemmJob& jo
 // vector path when its chunk lies inside an aligned operand.
 template <typename T, typename TL>
 GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
-                           typename MfmaOp<T>::acc_t (&acc)[4][4], T (*As)[GEMM_BK][GEMM_BM + LDS_PAD],
-                           T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
-  typedef MfmaOp<T> Op;
+                                   typename MfmaOp<T>::acc_t (&acc)[4][4], LdsBuf<T> As, LdsBuf<T> Bs) {
+  constexpr int BK = Chunk<T>::BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int send = job.seg0 + job.nseg;
@@ -157,18 +191,18 @@ GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict
     if (ck0 < cke) break;
   }
   if (cs >= send) return;
-  TL ra[8], rb[8];
+  TL ra[Chunk<T>::E], rb[Chunk<T>::E];
   {
     const GemmSeg& s = segs[cs];
-    load_chunk<TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, ck0, cke, tid, ra);
-    load_chunk<TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, ck0, cke, tid, rb);
+    load_chunk<T, TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, ck0, cke, tid, ra);
+    load_chunk<T, TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, ck0, cke, tid, rb);
     store_chunk<T, TL>(As[0], s.modeA, tid, ra);
     store_chunk<T, TL>(Bs[0], s.modeB, tid, rb);
   }
   __syncthreads();
   int buf = 0;
   while (true) {
-    int ns = cs, nk0 = ck0 + GEMM_BK, nke = cke;
+    int ns = cs, nk0 = ck0 + BK, nke = cke;
     if (nk0 >= cke) {
       for (ns = cs + 1; ns < send; ++ns) {
         seg_krange<T>(segs[ns], m0, n0, nk0, nke);
@@ -181,23 +215,12 @@ GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict
       const GemmSeg& s = segs[ns];
       nmodeA = s.modeA;
       nmodeB = s.modeB;
-      load_chunk<TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, nk0, nke, tid, ra);
-      load_chunk<TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, nk0, nke, tid, rb);
+      load_chunk<T, TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, nk0, nke, tid, ra);
+      load_chunk<T, TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, nk0, nke, tid, rb);
     }
-#pragma unroll
-    for (int kq = 0; kq < GEMM_BK / 4; ++kq) {
-      const int kr = kq * 4 + (lane >> 4);
-      T a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
-    }
+    mma_chunk<T>(As[buf], Bs[buf], lane, wm, wn, acc);
     if (!more) break;
+    // keep the stores of the next chunk (which wait for its global loads) after the products
     __builtin_amdgcn_sched_barrier(0);
     store_chunk<T, TL>(As[buf ^ 1], nmodeA, tid, ra);
     store_chunk<T, TL>(Bs[buf ^ 1], nmodeB, tid, rb);
@@ -210,48 +233,30 @@ GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict
 }
 
 // Unguarded chunk load for a macro tile that lies inside the operand with 16-byte aligned
-// rows (the caller has checked): KC, 2 consecutive k of 4 rows per thread; MC, 8
-// consecutive rows of one k per thread.
-template <typename TL, int MODE>
-GPR_DEV void load_chunk_full(const TL* __restrict__ P, int64_t ld, int base, int k0, int tid, TL (&r)[8]) {
+// rows (the caller has checked); the patterns of load_chunk for a fixed mode.
+template <typename T, typename TL, int MODE>
+GPR_DEV void load_chunk_full(const TL* __restrict__ P, int64_t ld, int base, int k0, int tid,
+                             TL (&r)[Chunk<T>::E]) {
+  typedef Chunk<T> C;
   if (MODE == MODE_KC) {
-    typedef TL v2 __attribute__((ext_vector_type(2)));
-    const int kk = k0 + (tid & 7) * 2;
+    typedef TL vk __attribute__((ext_vector_type(C::KPT)));
+    const int kk = k0 + (tid & 7) * C::KPT;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      const v2 v = load_global<v2>(P + (int64_t)(base + (tid >> 3) + 32 * p) * ld + kk);
-      r[2 * p] = v[0];
-      r[2 * p + 1] = v[1];
+      const vk v = load_global<vk>(P + (int64_t)(base + (tid >> 3) + 32 * p) * ld + kk);
+#pragma unroll
+      for (int e = 0; e < C::KPT; ++e) r[p * C::KPT + e] = v[e];
     }
   } else {
     constexpr int VEC = 16 / sizeof(TL);
     typedef TL vv __attribute__((ext_vector_type(VEC)));
-    const TL* q = P + (int64_t)(k0 + (tid >> 4)) * ld + base + (tid & 15) * 8;
+    const TL* q = P + (int64_t)(k0 + tid / C::TPR) * ld + base + (tid % C::TPR) * C::E;
 #pragma unroll
-    for (int e = 0; e < 8; e += VEC) {
+    for (int e = 0; e < C::E; e += VEC) {
       const vv v = load_global<vv>(q + e);
 #pragma unroll
       for (int x = 0; x < VEC; ++x) r[e + x] = v[x];
     }
-  }
-}
-
-template <typename T>
-GPR_DEV void mma_chunk(const T (*As)[GEMM_BM + LDS_PAD], const T (*Bs)[GEMM_BN + LDS_PAD], int lane, int wm, int wn,
-                       typename MfmaOp<T>::acc_t (&acc)[4][4]) {
-  typedef MfmaOp<T> Op;
-#pragma unroll
-  for (int kq = 0; kq < GEMM_BK / 4; ++kq) {
-    const int kr = kq * 4 + (lane >> 4);
-    T a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
   }
 }
 
@@ -260,22 +265,23 @@ GPR_DEV void mma_chunk(const T (*As)[GEMM_BM + LDS_PAD], const T (*Bs)[GEMM_BN +
 // Starts with a barrier, so the previous segment's last chunk may still be in LDS.
 template <typename T, typename TL, int MA, int MB>
 GPR_DEV void seg_full(const GemmSeg& s, int m0, int n0, int kb, int ke, typename MfmaOp<T>::acc_t (&acc)[4][4],
-                      T (*As)[GEMM_BK][GEMM_BM + LDS_PAD], T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
+                      LdsBuf<T> As, LdsBuf<T> Bs) {
+  constexpr int BK = Chunk<T>::BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const TL* __restrict__ A = (const TL*)s.A;
   const TL* __restrict__ B = (const TL*)s.B;
-  TL ra[8], rb[8];
-  load_chunk_full<TL, MA>(A, s.lda, m0, kb, tid, ra);
-  load_chunk_full<TL, MB>(B, s.ldb, n0, kb, tid, rb);
+  TL ra[Chunk<T>::E], rb[Chunk<T>::E];
+  load_chunk_full<T, TL, MA>(A, s.lda, m0, kb, tid, ra);
+  load_chunk_full<T, TL, MB>(B, s.ldb, n0, kb, tid, rb);
   __syncthreads();
   store_chunk<T, TL>(As[0], MA, tid, ra);
   store_chunk<T, TL>(Bs[0], MB, tid, rb);
   __syncthreads();
   int buf = 0;
-  for (int k0 = kb; k0 + GEMM_BK < ke; k0 += GEMM_BK) {
-    load_chunk_full<TL, MA>(A, s.lda, m0, k0 + GEMM_BK, tid, ra);
-    load_chunk_full<TL, MB>(B, s.ldb, n0, k0 + GEMM_BK, tid, rb);
+  for (int k0 = kb; k0 + BK < ke; k0 += BK) {
+    load_chunk_full<T, TL, MA>(A, s.lda, m0, k0 + BK, tid, ra);
+    load_chunk_full<T, TL, MB>(B, s.ldb, n0, k0 + BK, tid, rb);
     mma_chunk<T>(As[buf], Bs[buf], lane, wm, wn, acc);
     // keep the stores of the next chunk (which wait for its global loads) after the products
     __builtin_amdgcn_sched_barrier(0);
@@ -290,13 +296,12 @@ GPR_DEV void seg_full(const GemmSeg& s, int m0, int n0, int kb, int ke, typename
 // Operand-mode specialisations of the main loop.  SPEC_GUARDED runs the guarded loop; the
 // others run the straight-line loop of one operand-mode pair and are chosen by the host
 // only for launches whose jobs all cover whole macro tiles (M, N multiples of 128), whose
-// segments all have K a multiple of 16, 16-byte aligned rows and that mode pair.
+// segments all have K a multiple of the chunk depth, 16-byte aligned rows and that pair.
 enum { SPEC_GUARDED = -1, SPEC_KK = 0, SPEC_KM = 1, SPEC_MM = 3 };
 
 template <typename T, typename TL, int SPEC>
 GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
-                           typename MfmaOp<T>::acc_t (&acc)[4][4], T (*As)[GEMM_BK][GEMM_BM + LDS_PAD],
-                           T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD]) {
+                           typename MfmaOp<T>::acc_t (&acc)[4][4], LdsBuf<T> As, LdsBuf<T> Bs) {
   if constexpr (SPEC == SPEC_GUARDED) {
     gemm_mainloop_generic<T, TL>(job, segs, m0, n0, acc, As, Bs);
   } else {
@@ -313,9 +318,9 @@ template <typename T, typename TL, int SPEC>
 GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
   typedef MfmaOp<T> Op;
   typedef typename Op::acc_t acc_t;
-  __shared__ __align__(16) char smem[SMEM_BYTES];
-  T (*As)[GEMM_BK][GEMM_BM + LDS_PAD] = reinterpret_cast<T (*)[GEMM_BK][GEMM_BM + LDS_PAD]>(smem);
-  T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD] = As + 2;
+  __shared__ __align__(16) char smem[Chunk<T>::SMEM];
+  LdsBuf<T> As = reinterpret_cast<LdsBuf<T>>(smem);
+  LdsBuf<T> Bs = As + 2;
   GemmJob job;
   int m0, n0;
   if (!locate_job(jobs, njobs, job, m0, n0)) return;
@@ -396,9 +401,9 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
                        TraceArgs ta) {
   typedef MfmaOp<T> Op;
   typedef typename Op::acc_t acc_t;
-  __shared__ __align__(16) char smem[SMEM_BYTES];
-  T (*As)[GEMM_BK][GEMM_BM + LDS_PAD] = reinterpret_cast<T (*)[GEMM_BK][GEMM_BM + LDS_PAD]>(smem);
-  T (*Bs)[GEMM_BK][GEMM_BN + LDS_PAD] = As + 2;
+  __shared__ __align__(16) char smem[Chunk<T>::SMEM];
+  LdsBuf<T> As = reinterpret_cast<LdsBuf<T>>(smem);
+  LdsBuf<T> Bs = As + 2;
   __shared__ double red[3][GEMM_THREADS];
   GemmJob job;
   int m0, n0;
@@ -459,8 +464,9 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 }
 
 // Host: the specialised main loop a launch may use (SPEC_GUARDED if any job or segment
-// needs guards or the segments mix operand modes).  esize: bytes per stored operand element.
-int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int esize) {
+// needs guards or the segments mix operand modes).  esize: bytes per stored operand element;
+// bk: chunk depth of the launch's product type.
+int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int esize, int bk) {
   int spec = -2;
   auto aligned = [](const void* p, int64_t ld, int es) {
     return (((uintptr_t)p) & 15) == 0 && (ld * es) % 16 == 0;
@@ -470,7 +476,7 @@ int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int es
     if (J.M % GEMM_BM != 0 || J.N % GEMM_BN != 0) return SPEC_GUARDED;
     for (int q = J.seg0; q < J.seg0 + J.nseg; ++q) {
       const GemmSeg& S = segs[q];
-      if (S.K % GEMM_BK != 0 || !aligned(S.A, S.lda, esize) || !aligned(S.B, S.ldb, esize)) return SPEC_GUARDED;
+      if (S.K % bk != 0 || !aligned(S.A, S.lda, esize) || !aligned(S.B, S.ldb, esize)) return SPEC_GUARDED;
       const int sp = S.modeA * 2 + S.modeB;
       if (spec == -2) spec = sp;
       else if (spec != sp) return SPEC_GUARDED;

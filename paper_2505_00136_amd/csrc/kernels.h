@@ -18,9 +18,10 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
 hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int spec,
                              const TraceArgs& ta, hipStream_t st);
 // Straight-line main loop of one operand-mode pair (0: KC/KC, 1: KC/MC, 3: MC/MC) when every
-// job covers whole 128 x 128 macro tiles and every segment has K % 16 == 0, 16-byte aligned
-// rows and that pair; -1 (guarded loop) otherwise.  esize: bytes per stored operand element.
-int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int esize);
+// job covers whole 128 x 128 macro tiles and every segment has K a multiple of the chunk
+// depth bk of the main loop, 16-byte aligned rows and that pair;
+// -1 (guarded loop) otherwise.  esize: bytes per stored operand element.
+int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int esize, int bk);
 
 // gemm_bf16.hip: trailing update from split-bfloat16 planes (nprod 3 or 6); KC operands only
 hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, hipStream_t st);

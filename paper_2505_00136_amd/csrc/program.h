@@ -136,8 +136,9 @@ struct Program {
       return;
     }
     const int esize = (f32 || kind == GEMM_KIND_WIDEN) ? 4 : 8;
+    const int bk = 16;   // chunk depth of the main loop (both product types)
     const int spec = (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
-                         ? -1 : gemm_launch_spec(jobs.data() + job0, nj, segs.data(), esize);
+                         ? -1 : gemm_launch_spec(jobs.data() + job0, nj, segs.data(), esize, bk);
     if (timed) (void)hipEventRecord(ea, sx);
     if (kind == GEMM_KIND_TRACE) {
       TraceArgs ta = *trace;
