@@ -1,0 +1,146 @@
+"""GPU checks at the benchmark's full size: n = 65536 training points, D = 128, 8192 test
+points, tile 2048, the hyperparameters and data of bench.py (so the same launches run).
+
+The oracle cannot factor K at this size, so the checks use outputs it computes one at a
+time -- sampled rows of K alpha, sampled entries of L L^T, sampled posterior means -- and
+properties that hold at any size: the variance lies in [0, nu] and the var-only path
+agrees with the diagonal of the full covariance, the gradient agrees with central
+differences of the library's own NLML, and the float32 trailing-update path agrees with
+the float64 one within the mixed-precision bounds.
+
+Tolerances (float64, kappa(K) ~ 1e4 here): a backward-stable factorisation gives
+|L L^T - K|_ij <= c n eps nu (n eps = 7e-12), hence 1e-10 nu; the solve residual
+|K alpha - y|_i is bounded the same way times |alpha|, hence 1e-9 max|y|; a posterior
+mean recomputed from the same alpha differs only in summation order, hence 1e-12.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from tests.tiles import lower_row  # noqa: E402
+
+N, M, D, TILE, SEED = 65536, 8192, 128, 2048, 3
+H = (math.sqrt(D), 1.0, 0.01)
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_00136_amd import _lib
+    _lib.load()
+    print(f"[fullsize] n={N} m={M} D={D} tile={TILE}: data", flush=True)
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=N, n_test=M, D=D, seed=SEED))
+    dev = torch.device("cuda:0")
+    Z, Zs, y = (torch.tensor(a, device=dev) for a in (ds.Z, ds.Zs, ds.y))
+    wsb = max(_lib.gpr_workspace_size(N, M, D, TILE, p) for p in ("fp64", "fp32"))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    K = torch.empty(_lib.gpr_tiles_bytes(N, TILE, "fp64"), dtype=torch.uint8, device=dev)
+
+    def fit(h, prec="fp64", Kbuf=None, sweeps=0):
+        Kb = K if Kbuf is None else Kbuf
+        alpha = torch.empty(N, dtype=torch.float64, device=dev)
+        nl = torch.empty(1, dtype=torch.float64, device=dev)
+        _lib.gpr_assemble(Z, N, D, h, TILE, prec, Kb)
+        info = _lib.gpr_cholesky(Kb, N, TILE, prec, ws, wsb)
+        assert info == 0
+        _lib.gpr_solve(Kb, Z, N, D, h, TILE, prec, y, alpha, sweeps, ws, wsb)
+        _lib.gpr_nlml(Kb, N, TILE, prec, y, alpha, nl)
+        return alpha, float(nl.item())
+
+    print("[fullsize] float64 fit", flush=True)
+    alpha, nlml = fit(H)
+    mean = torch.empty(M, dtype=torch.float64, device=dev)
+    var = torch.empty(M, dtype=torch.float64, device=dev)
+    _lib.gpr_predict(Z, N, Zs, M, D, H, alpha, mean, ws, wsb)
+    _lib.gpr_predict_var(Z, N, Zs, M, D, H, K, TILE, "fp64", False, False, var, ws, wsb)
+    torch.cuda.synchronize()
+    return dict(lib=_lib, ds=ds, Z=Z, Zs=Zs, y=y, K=K, ws=ws, wsb=wsb, fit=fit, alpha=alpha,
+                alpha_h=alpha.cpu().numpy(), nlml=nlml, mean=mean.cpu().numpy(), var=var.cpu().numpy())
+
+
+def test_sampled_solve_residual(full):
+    ds, a = full["ds"], full["alpha_h"]
+    ell, nu, s2 = H
+    rows = np.random.default_rng(11).choice(N, 64, replace=False)
+    r = oracle.se_cov(ds.Z[rows], ds.Z, ell, nu) @ a + s2 * a[rows] - ds.y[rows]
+    assert np.max(np.abs(r)) <= 1e-9 * np.max(np.abs(ds.y))
+
+
+def test_sampled_factor_entries(full):
+    ds, K = full["ds"], full["K"]
+    ell, nu, s2 = H
+    rng = np.random.default_rng(12)
+    pairs = [(int(i), int(rng.integers(0, i + 1))) for i in rng.choice(N, 24, replace=False)]
+    pairs += [(N - 1, N - 1), (N - 1, 0), (TILE, TILE - 1), (0, 0)]
+    for i, j in pairs:
+        li, lj = lower_row(K, N, TILE, 8, i), lower_row(K, N, TILE, 8, j)
+        llt = float(np.dot(li[: j + 1], lj[: j + 1]))
+        kij = float(oracle.se_cov(ds.Z[i:i + 1], ds.Z[j:j + 1], ell, nu)[0, 0]) + (s2 if i == j else 0.0)
+        assert abs(llt - kij) <= 1e-10 * nu, (i, j, llt, kij)
+
+
+def test_sampled_posterior_mean(full):
+    ds, a = full["ds"], full["alpha_h"]
+    ell, nu, _ = H
+    rows = np.random.default_rng(13).choice(M, 64, replace=False)
+    ref = oracle.se_cov(ds.Zs[rows], ds.Z, ell, nu) @ a
+    got = full["mean"][rows]
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(np.max(np.abs(ref)), 1.0)
+
+
+def test_variance_bounds_and_full_covariance(full):
+    lib, var = full["lib"], full["var"]
+    _, nu, _ = H
+    assert np.all(var >= -1e-12 * nu) and np.all(var <= nu * (1 + 1e-12))
+    m = 256
+    Zs = full["Zs"][:m].contiguous()
+    S = torch.empty((m, m), dtype=torch.float64, device="cuda:0")
+    lib.gpr_predict_var(full["Z"], N, Zs, m, D, H, full["K"], TILE, "fp64", True, False, S, full["ws"], full["wsb"])
+    S = S.cpu().numpy()
+    assert np.max(np.abs(np.diag(S) - var[:m])) <= 1e-12 * nu
+    assert np.max(np.abs(S - S.T)) <= 1e-12 * nu
+
+
+def test_gradient_against_central_differences(full):
+    lib = full["lib"]
+    grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    lib.gpr_nlml_grad(full["Z"], N, D, H, full["K"], TILE, "fp64", full["alpha"], (1, 1, 1), grad, full["ws"],
+                      full["wsb"])
+    g = grad.cpu().numpy()
+    th = np.log(np.array(H))
+    hstep = 5e-4
+    fd = np.zeros(3)
+    for k in range(3):
+        f = []
+        for sgn in (1.0, -1.0):
+            t = th.copy()
+            t[k] += sgn * hstep
+            f.append(full["fit"](tuple(np.exp(t)))[1])
+        fd[k] = (f[0] - f[1]) / (2 * hstep)
+        print(f"[fullsize] d nlml / d log theta[{k}]: analytic {g[k]:.10e} central difference {fd[k]:.10e}", flush=True)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6 * np.max(np.abs(fd)))
+
+
+def test_float32_path_within_mixed_bounds(full):
+    lib = full["lib"]
+    K32 = torch.empty(lib.gpr_tiles_bytes(N, TILE, "fp32"), dtype=torch.uint8, device="cuda:0")
+    a32, nl32 = full["fit"](H, "fp32", K32, 3)
+    assert abs(nl32 - full["nlml"]) / abs(full["nlml"]) <= 1e-6
+    a = full["alpha_h"]
+    assert np.linalg.norm(a32.cpu().numpy() - a) / np.linalg.norm(a) <= 1e-8
+    mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+    lib.gpr_predict(full["Z"], N, full["Zs"], M, D, H, a32, mean, full["ws"], full["wsb"])
+    mref = full["mean"]
+    assert np.linalg.norm(mean.cpu().numpy() - mref) / np.linalg.norm(mref) <= 1e-6
+    var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+    lib.gpr_predict_var(full["Z"], N, full["Zs"], M, D, H, K32, TILE, "fp32", False, False, var, full["ws"],
+                        full["wsb"])
+    assert np.max(np.abs(var.cpu().numpy() - full["var"])) <= 1e-4

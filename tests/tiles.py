@@ -27,3 +27,20 @@ def winv_tiles(raw: np.ndarray, n: int, b: int):
 
 def diag_tile_offset_bytes(k: int, b: int) -> int:
     return k * b * b * 8
+
+
+def lower_row(buf, n: int, b: int, esize: int, i: int) -> np.ndarray:
+    """Row i (entries 0..i) of the lower factor held in a K_tiles buffer, reading only that
+    row's bytes; `buf` is the buffer as a flat uint8 torch tensor (device or host)."""
+    T = n // b
+    I, r = divmod(i, b)
+    parts = []
+    off0 = 2 * T * b * b * 8
+    dt = np.float64 if esize == 8 else np.float32
+    for J in range(I):
+        idx = J * (T - 1) - J * (J - 1) // 2 + (I - J - 1)
+        start = off0 + (idx * b * b + r * b) * esize
+        parts.append(buf[start:start + b * esize].cpu().numpy().view(dt).astype(np.float64))
+    start = (I * b * b + r * b) * 8
+    parts.append(buf[start:start + (r + 1) * 8].cpu().numpy().view(np.float64))
+    return np.concatenate(parts)
