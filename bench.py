@@ -1,7 +1,8 @@
 """Benchmark of the GP hot path on one MI355X.
 
 One step is one pass of the whole path over the n=65536, D=128 workload (8192 test
-points, tile 2048), in float64 and in the mixed precision: covariance assembly,
+points, tile 2048), in float64 and in the mixed precisions (FP32 trailing updates and the
+3-way split-bfloat16 products by default): covariance assembly,
 tiled Cholesky, alpha (with three float64 refinement sweeps in the mixed mode),
 NLML, posterior mean, posterior variance and the NLML gradient.  Inputs are resident
 in HBM before the timed region; every phase is timed with HIP events on the stream
@@ -304,7 +305,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n65536_d128", choices=sorted(WORKLOADS))
-    ap.add_argument("--precs", default="fp64,fp32")
+    ap.add_argument("--precs", default="fp64,fp32,bf16x6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter calibration) and exit")

@@ -1,0 +1,110 @@
+"""GPU parity at n = 16384 training points, D = 8, 4096 test points, tile 1024 (16 x 16
+tiles), the float64 configuration with full predictive covariance, NLML, gradient and
+10 Adam steps (lr 0.1) from theta = (0, 0, log 0.1).
+
+At this size the oracle still runs completely on the host (a 16384^2 Cholesky, a
+16384 x 4096 triangular solve, the explicit inverse for the gradient: tens of seconds),
+so every output is compared element by element: float64 tolerance 1e-10 relative (the
+kernel matrix is well conditioned here, kappa ~ 1e3-1e4), 1e-9 for the gradient, whose
+terms cancel.  The Adam trajectory is checked exactly for its first step (Adam's first
+step is theta_0 - lr g / (|g| + eps) per coordinate) and as a property afterwards (the
+NLML decreases over the 10 steps).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import Hyper
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N, M, D, TILE, SEED = 16384, 4096, 8, 1024, 2
+THETA0 = (0.0, 0.0, math.log(0.1))
+H = Hyper(1.0, 1.0, 0.1)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def run():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_00136_amd import _lib
+    _lib.load()
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=N, n_test=M, D=D, seed=SEED))
+    dev = torch.device("cuda:0")
+    Z, Zs, y = (torch.tensor(a, device=dev) for a in (ds.Z, ds.Zs, ds.y))
+    h = (H.lengthscale, H.signal_var, H.noise_var)
+    wsb = _lib.gpr_workspace_size(N, M, D, TILE, "fp64")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    K = torch.empty(_lib.gpr_tiles_bytes(N, TILE, "fp64"), dtype=torch.uint8, device=dev)
+    alpha = torch.empty(N, dtype=torch.float64, device=dev)
+    nl = torch.empty(1, dtype=torch.float64, device=dev)
+    mean = torch.empty(M, dtype=torch.float64, device=dev)
+    var = torch.empty(M, dtype=torch.float64, device=dev)
+    cov = torch.empty((M, M), dtype=torch.float64, device=dev)
+    grad = torch.empty(3, dtype=torch.float64, device=dev)
+    print(f"[n16384] device path", flush=True)
+    _lib.gpr_assemble(Z, N, D, h, TILE, "fp64", K)
+    assert _lib.gpr_cholesky(K, N, TILE, "fp64", ws, wsb) == 0
+    _lib.gpr_solve(K, Z, N, D, h, TILE, "fp64", y, alpha, 0, ws, wsb)
+    _lib.gpr_nlml(K, N, TILE, "fp64", y, alpha, nl)
+    _lib.gpr_predict(Z, N, Zs, M, D, h, alpha, mean, ws, wsb)
+    _lib.gpr_predict_var(Z, N, Zs, M, D, h, K, TILE, "fp64", False, False, var, ws, wsb)
+    _lib.gpr_predict_var(Z, N, Zs, M, D, h, K, TILE, "fp64", True, False, cov, ws, wsb)
+    _lib.gpr_nlml_grad(Z, N, D, h, K, TILE, "fp64", alpha, (1, 1, 1), grad, ws, wsb)
+    th1, _, _ = _lib.gpr_optimize(Z, y, N, D, TILE, "fp64", THETA0, (1, 1, 1), 1, 0.1, 0.9, 0.999, 1e-8, None,
+                                  K, ws, wsb)
+    th, st, trace = _lib.gpr_optimize(Z, y, N, D, TILE, "fp64", THETA0, (1, 1, 1), 10, 0.1, 0.9, 0.999, 1e-8, None,
+                                      K, ws, wsb)
+    torch.cuda.synchronize()
+    got = dict(alpha=alpha.cpu().numpy(), nlml=float(nl.item()), mean=mean.cpu().numpy(), var=var.cpu().numpy(),
+               cov=cov.cpu().numpy(), grad=grad.cpu().numpy(), theta1=np.array(th1), theta=np.array(th),
+               trace=np.array(trace))
+    print(f"[n16384] oracle fit", flush=True)
+    L, a, f = oracle.fit(ds.Z, ds.y, H)
+    ref = dict(alpha=a, nlml=f, mean=oracle.predict_mean(ds.Z, ds.Zs, H, a))
+    print(f"[n16384] oracle covariance", flush=True)
+    ref["cov"] = oracle.predict_var(ds.Z, ds.Zs, H, L, full_cov=True)
+    ref["var"] = oracle.predict_var(ds.Z, ds.Zs, H, L)
+    print(f"[n16384] oracle gradient", flush=True)
+    ref["grad"] = oracle.nlml_grad(ds.Z, H, L, a)
+    return got, ref
+
+
+def test_alpha_nlml_mean(run):
+    got, ref = run
+    assert _rel(got["alpha"], ref["alpha"]) < 1e-10
+    assert abs(got["nlml"] - ref["nlml"]) / abs(ref["nlml"]) < 1e-10
+    assert _rel(got["mean"], ref["mean"]) < 1e-10
+
+
+def test_variance_and_full_covariance(run):
+    got, ref = run
+    assert _rel(got["var"], ref["var"]) < 1e-10
+    assert _rel(got["cov"], ref["cov"]) < 1e-10
+    assert np.max(np.abs(np.diag(got["cov"]) - got["var"])) <= 1e-12
+
+
+def test_gradient(run):
+    got, ref = run
+    np.testing.assert_allclose(got["grad"], ref["grad"], rtol=1e-9, atol=1e-9 * np.max(np.abs(ref["grad"])))
+
+
+def test_adam_steps(run):
+    got, ref = run
+    trace = got["trace"]
+    assert trace.shape == (11,)
+    assert abs(trace[0] - ref["nlml"]) / abs(ref["nlml"]) < 1e-10          # NLML at theta_0
+    assert trace[-1] < trace[0]
+    # the optimiser's first step from the oracle's gradient at theta_0
+    g = ref["grad"]
+    th1 = np.array(THETA0) - 0.1 * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(got["theta1"], th1, rtol=1e-12, atol=1e-12)
+    assert np.all(np.isfinite(got["theta"]))
