@@ -145,11 +145,48 @@ int upload_tables(const Program& P, void* arena, size_t cap, hipStream_t st, con
   return upload_blob(blob.data(), bytes, arena, st);
 }
 
+// Auxiliary stream (default priority, non-blocking) and event pool of the look-ahead, per
+// device, created on first use and kept for the life of the process.
+struct AuxState {
+  std::mutex mu;
+  int dev = -1;
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> events;
+};
+AuxState g_aux;
+
+int aux_resources(int nevents, hipStream_t* aux, std::vector<hipEvent_t>** evs) {
+  std::lock_guard<std::mutex> lk(g_aux.mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (g_aux.dev != dev) {
+    g_aux.aux = nullptr;
+    g_aux.events.clear();
+    g_aux.dev = dev;
+  }
+  if (!g_aux.aux) HIPCHK(hipStreamCreateWithFlags(&g_aux.aux, hipStreamNonBlocking));
+  while ((int)g_aux.events.size() < nevents) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    g_aux.events.push_back(e);
+  }
+  *aux = g_aux.aux;
+  *evs = &g_aux.events;
+  return GPR_OK;
+}
+
 // Runs a program description: record pass, table upload into `arena`, execute pass.
+// nevents > 0 gives the description the auxiliary stream and that many events.
 template <typename F>
-int run_program(F&& describe, void* arena, size_t arena_cap, hipStream_t st, int64_t* trace_wg = nullptr) {
+int run_program(F&& describe, void* arena, size_t arena_cap, hipStream_t st, int64_t* trace_wg = nullptr,
+                int nevents = 0) {
   Program P;
   P.st = st;
+  P.aux = st;
+  if (nevents > 0) {
+    int rc = aux_resources(nevents, &P.aux, &P.events);
+    if (rc) return rc;
+  }
   describe(P);
   const size_t nj = P.jobs.size(), ns = P.segs.size();
   const GemmJob* dj = nullptr;
@@ -169,7 +206,7 @@ int run_program(F&& describe, void* arena, size_t arena_cap, hipStream_t st, int
 
 // ================================================================ Cholesky
 struct CholWs {
-  unsigned long long* info;
+  unsigned long long* info;   // [0]: first failing pivot (atomic min), [2]: its copy for the host
   void* panel;      // copy of the panel below the diagonal tile (TRSM source)
   float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
   uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2, two sets
@@ -178,9 +215,9 @@ struct CholWs {
   size_t arena_cap;
 };
 
-void describe_diag_and_panel(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
-  const int64_t b = L.b, T = L.T;
-  const bool mixed = is_mixed(prec);
+// POTRF of diagonal tile k with its inverse: the blocked loop described at describe_cholesky.
+void describe_diag(Program& P, const TileLayout& L, void* K, const CholWs& w, int64_t k) {
+  const int64_t b = L.b;
   double* Dk = L.diag(K, k);
   double* Wk = L.winv(K, k);
   P.kernel([=](hipStream_t s) { return launch_set_identity(Wk, b, s); });
@@ -208,25 +245,45 @@ void describe_diag_and_panel(Program& P, const TileLayout& L, void* K, int prec,
     }
   }
   P.kernel([=](hipStream_t s) { return launch_zero_upper(Dk, b, s); });
-  if (k == T - 1) return;
-  void* panel = L.off(K, k + 1, k);
-  const int64_t prow = (T - k - 1) * b;
-  const size_t pbytes = (size_t)prow * b * L.esize;
+}
+
+// Inputs of the TRSM of panel k (block column k below the diagonal): a copy of the panel
+// (the product is computed in place) and, in the mixed modes, a float32 copy of L_kk^{-1}.
+void describe_panel_copy(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
+  const int64_t b = L.b, T = L.T;
+  if (k >= T - 1) return;
+  const void* panel = L.off(K, k + 1, k);
+  const size_t pbytes = (size_t)(T - k - 1) * b * b * L.esize;
   P.kernel([=](hipStream_t s) { return launch_copy(w.panel, panel, pbytes, s); });
-  if (mixed) P.kernel([=](hipStream_t s) { return launch_convert_f64_f32(Wk, w.w32, b * b, s); });
-  // TRSM: panel = panel_copy * W_kk^T
-  P.gemm_begin(mixed);
-  P.job(panel, b, nullptr, 0, prow, b, 1.0, 0.0, mixed ? JOB_C_F32 : 0);
-  P.seg(w.panel, b, MODE_KC, mixed ? (const void*)w.w32 : (const void*)Wk, b, MODE_KC, b, B_LOWER);
-  P.gemm_end();
-  if (is_bf16(prec)) {
-    const int64_t pstride = (T - 1) * b * b;
-    uint16_t* pl = w.planes + (k & 1) * 3 * pstride;
-    P.kernel([=](hipStream_t s) {
-      return launch_split_bf16x3((const float*)panel, prow * b, pl, pl + pstride,
-                                 prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr, s);
-    });
+  if (is_mixed(prec)) {
+    const double* Wk = L.winv(K, k);
+    P.kernel([=](hipStream_t s) { return launch_convert_f64_f32(Wk, w.w32, b * b, s); });
   }
+}
+
+// Adds the TRSM of panel k, X = A_panel L_kk^{-T} (one job against the inverse), to the
+// open launch; returns its algorithmic flops.
+double add_trsm_job(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
+  const int64_t b = L.b, T = L.T;
+  if (k >= T - 1) return 0.0;
+  const bool mixed = is_mixed(prec);
+  const int64_t prow = (T - k - 1) * b;
+  P.job(L.off(K, k + 1, k), b, nullptr, 0, prow, b, 1.0, 0.0, mixed ? JOB_C_F32 : 0);
+  P.seg(w.panel, b, MODE_KC, mixed ? (const void*)w.w32 : (const void*)L.winv(K, k), b, MODE_KC, b, B_LOWER);
+  const double bd = (double)b;
+  return (double)(T - k - 1) * bd * bd * (bd + 1.0);
+}
+
+// hi/mid(/lo) bfloat16 planes of the solved panel k (split modes), buffer set k mod 2.
+void describe_split(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
+  const int64_t b = L.b, T = L.T;
+  if (!is_bf16(prec) || k >= T - 1) return;
+  const int64_t pstride = (T - 1) * b * b, count = (T - k - 1) * b * b;
+  const float* panel = (const float*)L.off(K, k + 1, k);
+  uint16_t* pl = w.planes + (k & 1) * 3 * pstride;
+  P.kernel([=](hipStream_t s) {
+    return launch_split_bf16x3(panel, count, pl, pl + pstride, prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr, s);
+  });
 }
 
 // Trailing update of step k restricted to block columns [n0, n1) (SYRK on diagonal tiles,
@@ -258,10 +315,8 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
     }
     P.gemm_end();
   }
-  {
-    const int kind = !split ? GEMM_KIND_UPDATE : (prec == GPR_BF16X6 ? GEMM_KIND_BF16X6 : GEMM_KIND_BF16X3);
-    P.gemm_begin(mixed, kind, mixed ? gemm_flops : syrk_flops + gemm_flops);
-  }
+  const int kind = !split ? GEMM_KIND_UPDATE : (prec == GPR_BF16X6 ? GEMM_KIND_BF16X6 : GEMM_KIND_BF16X3);
+  P.gemm_begin(mixed, kind, mixed ? gemm_flops : syrk_flops + gemm_flops);
   for (int64_t nn = n0; nn < n1; ++nn) {
     for (int64_t m = nn; m < T; ++m) {
       if (m == nn) {
@@ -282,23 +337,65 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // The tiled right-looking factorisation (Fig. 1).  Step k: factor the diagonal tile
 // and invert its factor (POTRF), X_mk = A_mk L_kk^{-T} for the panel (TRSM, one GEMM
 // against the inverse), then A_mn -= X_mk X_nk^T over the trailing lower triangle
-// (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.  Each step's update is
-// issued as the next block column first (U1) and the remaining columns (U2), all in
-// the caller's stream.  The split-bfloat16 planes are double-buffered by step parity.
+// (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.
+//
+// Look-ahead: each step's update is issued as the next block column (U1) and the
+// remaining columns (U2).  The factorisation of diagonal tile k+1 and the solve of its
+// panel run on the auxiliary stream as soon as U1 is done, overlapping U2 on the caller's
+// stream; events order the two (e1(k): U1 of step k done, e2(k): panel k solved).  The
+// two streams touch disjoint tiles: U2 reads block column k and writes columns >= k+2,
+// the look-ahead work reads and writes block column k+1, diagonal tile k+1 and its
+// inverse, the panel copy and (split modes) the bfloat16 planes of panel k+1, which are
+// double-buffered by step parity.  The panel is staged by a copy kernel: a runtime
+// device-to-device copy issued on the auxiliary stream read stale panel data produced by
+// U1 on the other stream (run-to-run differences of 1e-5 in the solve residual at
+// n = 65536), which the copy kernel does not.
 //
 // The diagonal tile itself is factored by a blocked right-looking loop with blocks of
 // 64; its inverse W is accumulated in the same loop: starting from W = I, block
 // step j multiplies block row j of W by the block inverse W_jj and subtracts
 // P_j (W_jj W_j) from the rows below, P_j being the block column of L below the
 // diagonal block; that update shares its launch with the trailing update P_j P_j^T.
+int chol_events_needed(int64_t T) { return 1 + 2 * (int)T; }
+
 void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w) {
   const int64_t T = L.T;
-  describe_diag_and_panel(P, L, K, prec, w, 0);
+  auto diag_and_panel = [&](int64_t k) {
+    describe_diag(P, L, K, w, k);
+    describe_panel_copy(P, L, K, prec, w, k);
+    if (k < T - 1) {
+      P.gemm_begin(is_mixed(prec));
+      add_trsm_job(P, L, K, prec, w, k);
+      P.gemm_end();
+    }
+    describe_split(P, L, K, prec, w, k);
+  };
+  auto e1 = [](int64_t k) { return 1 + 2 * (int)k; };
+  auto e2 = [](int64_t k) { return 2 + 2 * (int)k; };
+  unsigned long long* info = w.info;
+  P.on(0);
+  P.kernel([=](hipStream_t s) { return launch_fill_u64(info, ~0ull, 2, s); });
+  P.record(0);
+  P.on(1);
+  P.wait(0);
+  diag_and_panel(0);
+  P.record(e2(0));
   for (int64_t k = 0; k + 1 < T; ++k) {
+    P.on(0);
+    P.wait(e2(k));
     describe_update(P, L, K, prec, w, k, k + 1, k + 2);   // U1: block column k+1
+    P.record(e1(k));
     describe_update(P, L, K, prec, w, k, k + 2, T);       // U2: the remaining columns
-    describe_diag_and_panel(P, L, K, prec, w, k + 1);
+    P.on(1);
+    P.wait(e1(k));
+    diag_and_panel(k + 1);
+    P.record(e2(k + 1));
   }
+  P.on(0);
+  P.wait(e2(T - 1));
+  // the first failing pivot (written by atomics on the auxiliary stream), copied by a kernel
+  // on the caller's stream into the slot the host reads
+  P.kernel([=](hipStream_t s) { return launch_copy(info + 2, info, 2 * sizeof(unsigned long long), s); });
 }
 
 struct CholSizes {
@@ -631,10 +728,14 @@ size_t chol_ws_bytes(const TileLayout& L, int prec) {
 int chol_impl(void* K, const TileLayout& L, int prec, void* ws, size_t ws_bytes, unsigned long long** info_out,
               hipStream_t st) {
   CholWs w = carve_chol(ws, L, prec, ws_bytes);
-  if (info_out) *info_out = w.info;
-  HIPCHK(hipMemsetAsync(w.info, 0xFF, sizeof(unsigned long long), st));
+  if (info_out) *info_out = w.info + 2;   // set by the factorisation's last kernel
 
-  return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w); }, w.arena, w.arena_cap, st);
+  // the auxiliary stream and events are shared by all calls of this process: serialise
+  // factorisations so that one call's events are not re-recorded by another
+  static std::mutex chol_mu;
+  std::lock_guard<std::mutex> lk(chol_mu);
+  return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w); }, w.arena, w.arena_cap, st, nullptr,
+                     chol_events_needed(L.T));
 }
 
 }  // namespace

@@ -38,6 +38,7 @@ hipError_t launch_zero_upper(double* A, int64_t b, hipStream_t st);
 hipError_t launch_convert_f64_f32(const double* src, float* dst, int64_t count, hipStream_t st);
 // device copy with a kernel on `st` (16-byte vectors when aligned)
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t st);
 
 // assemble.hip
 // Lower tiles of K (Eq. 2) into the tiled layout: region D (float64) and region O (esize 8 or 4).

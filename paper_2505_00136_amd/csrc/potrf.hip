@@ -50,13 +50,50 @@ hipError_t launch_zero_upper(double* A, int64_t b, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void copy4_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n4) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void copy1_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Device-to-device copies are kernels (16-, 4- or 1-byte elements by alignment), never the
+// runtime's copy: a runtime copy on one stream of data a kernel on another stream produced
+// was observed to read stale data despite the event ordering them.
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;
-  if ((((uintptr_t)dst | (uintptr_t)src | bytes) & 15) != 0) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
-  const int64_t n16 = (int64_t)(bytes / 16);
-  int64_t g = (n16 + 255) / 256;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)g), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n16);
+  const uintptr_t al = (uintptr_t)dst | (uintptr_t)src | bytes;
+  if ((al & 15) == 0) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    int64_t g = (n16 + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)g), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n16);
+  } else if ((al & 3) == 0) {
+    const int64_t n4 = (int64_t)(bytes / 4);
+    int64_t g = (n4 + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(copy4_kernel, dim3((unsigned)g), dim3(256), 0, st, (const uint32_t*)src, (uint32_t*)dst, n4);
+  } else {
+    const int64_t n = (int64_t)bytes;
+    int64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(copy1_kernel, dim3((unsigned)g), dim3(256), 0, st, (const unsigned char*)src, (unsigned char*)dst,
+                       n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
   return hipGetLastError();
 }
 

@@ -43,6 +43,12 @@ inline TimingLog g_timing;
 struct Program {
   bool exec = false;
   hipStream_t st = nullptr;        // the caller's stream
+  // Look-ahead: a second stream (default priority) and events ordering the two; launches go
+  // to the stream selected by on() (0: caller's, 1: auxiliary).  With no events (aux ==
+  // st), record() and wait() do nothing and every launch stays in the caller's stream.
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t>* events = nullptr;
+  int cur = 0;
   std::vector<GemmJob> jobs;
   std::vector<GemmSeg> segs;
   const GemmJob* djobs = nullptr;
@@ -57,7 +63,17 @@ struct Program {
   const TraceArgs* trace = nullptr;
   int64_t trace_wg = 0, trace_cap = 0;
 
-  hipStream_t stream() const { return st; }
+  hipStream_t stream() const { return cur == 1 && aux ? aux : st; }
+  void on(int s) { cur = s; }
+  // Event ev is recorded on / waited for by the current stream (execute pass only).
+  void record(int ev) {
+    if (!exec || err != hipSuccess || !events || ev >= (int)events->size()) return;
+    err = hipEventRecord((*events)[ev], stream());
+  }
+  void wait(int ev) {
+    if (!exec || err != hipSuccess || !events || ev >= (int)events->size()) return;
+    err = hipStreamWaitEvent(stream(), (*events)[ev], 0);
+  }
 
   void reset_for_exec(const GemmJob* dj, const GemmSeg* ds) {
     exec = true;

@@ -109,6 +109,12 @@ def test_variance_bounds_and_full_covariance(full):
     assert np.max(np.abs(S - S.T)) <= 1e-12 * nu
 
 
+def test_factorisation_bitwise_reproducible(full):
+    """The factorisation runs on two streams (look-ahead); a repeat must give the same bits."""
+    alpha2, nlml2 = full["fit"](H)
+    assert torch.equal(alpha2, full["alpha"]) and nlml2 == full["nlml"]
+
+
 def test_gradient_against_central_differences(full):
     lib = full["lib"]
     grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
