@@ -5,8 +5,8 @@ The oracle cannot factor K at this size, so the checks use outputs it computes o
 time -- sampled rows of K alpha, sampled entries of L L^T, sampled posterior means -- and
 properties that hold at any size: the variance lies in [0, nu] and the var-only path
 agrees with the diagonal of the full covariance, the gradient agrees with central
-differences of the library's own NLML, and the float32 trailing-update path agrees with
-the float64 one within the mixed-precision bounds.
+differences of the library's own NLML, and the mixed paths (float32 trailing updates,
+3-way split bfloat16) agree with the float64 one within the mixed-precision bounds.
 
 Tolerances (float64, kappa(K) ~ 1e4 here): a backward-stable factorisation gives
 |L L^T - K|_ij <= c n eps nu (n eps = 7e-12), hence 1e-10 nu; the solve residual
@@ -40,7 +40,7 @@ def full():
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=N, n_test=M, D=D, seed=SEED))
     dev = torch.device("cuda:0")
     Z, Zs, y = (torch.tensor(a, device=dev) for a in (ds.Z, ds.Zs, ds.y))
-    wsb = max(_lib.gpr_workspace_size(N, M, D, TILE, p) for p in ("fp64", "fp32"))
+    wsb = max(_lib.gpr_workspace_size(N, M, D, TILE, p) for p in ("fp64", "fp32", "bf16x6"))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     K = torch.empty(_lib.gpr_tiles_bytes(N, TILE, "fp64"), dtype=torch.uint8, device=dev)
 
@@ -135,10 +135,13 @@ def test_gradient_against_central_differences(full):
     np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6 * np.max(np.abs(fd)))
 
 
-def test_float32_path_within_mixed_bounds(full):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_mixed_paths_within_bounds(full, prec):
+    """FP32 trailing updates and the 3-way split-bfloat16 products (hi/mid/lo, six products),
+    float64 diagonal tiles, 3 refinement sweeps: mean and NLML within 1e-6 of float64."""
     lib = full["lib"]
-    K32 = torch.empty(lib.gpr_tiles_bytes(N, TILE, "fp32"), dtype=torch.uint8, device="cuda:0")
-    a32, nl32 = full["fit"](H, "fp32", K32, 3)
+    K32 = torch.empty(lib.gpr_tiles_bytes(N, TILE, prec), dtype=torch.uint8, device="cuda:0")
+    a32, nl32 = full["fit"](H, prec, K32, 3)
     assert abs(nl32 - full["nlml"]) / abs(full["nlml"]) <= 1e-6
     a = full["alpha_h"]
     assert np.linalg.norm(a32.cpu().numpy() - a) / np.linalg.norm(a) <= 1e-8
@@ -147,6 +150,6 @@ def test_float32_path_within_mixed_bounds(full):
     mref = full["mean"]
     assert np.linalg.norm(mean.cpu().numpy() - mref) / np.linalg.norm(mref) <= 1e-6
     var = torch.empty(M, dtype=torch.float64, device="cuda:0")
-    lib.gpr_predict_var(full["Z"], N, full["Zs"], M, D, H, K32, TILE, "fp32", False, False, var, full["ws"],
+    lib.gpr_predict_var(full["Z"], N, full["Zs"], M, D, H, K32, TILE, prec, False, False, var, full["ws"],
                         full["wsb"])
     assert np.max(np.abs(var.cpu().numpy() - full["var"])) <= 1e-4
