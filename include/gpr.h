@@ -243,6 +243,20 @@ GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, doubl
  * library (Fig. 1): counts[0..3] = POTRF, TRSM, SYRK, GEMM tile tasks.  Host only. */
 GPR_API int gpr_cholesky_census(int64_t T, int64_t* counts);
 
+/* Dependency check of the factorisation's two-stream schedule (the task dependencies of
+ * Fig. 1 as ordering between launches), host only: runs the same description that
+ * gpr_cholesky executes for (n, tile, prec) in a pass that launches nothing, recording the
+ * byte ranges each launch reads and writes and the events between the caller's stream
+ * and the auxiliary stream, and replays it with vector clocks.  report[0..7] (host array
+ * of 8): launches, launches on the caller's stream, on the auxiliary stream, event waits,
+ * pairs of launches on different streams ordered in neither direction, such pairs that
+ * touch common bytes with at least one writing (a correct schedule has none), launches
+ * without access ranges, waits issued before their event was recorded.  omit_event >= 0
+ * analyses the schedule as if every wait on that event were missing (event 0: start,
+ * 1 + 2k: column k+1 of step k updated, 2 + 2k: panel k solved); -1 analyses it as issued.
+ * Touches no device memory.  Errors: GPR_ERR_PREC, GPR_ERR_SHAPE, GPR_ERR_ARG. */
+GPR_API int gpr_cholesky_schedule_check(int64_t n, int64_t tile, int prec, int64_t omit_event, int64_t* report);
+
 #ifdef __cplusplus
 }
 #endif

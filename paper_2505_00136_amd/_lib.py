@@ -44,6 +44,7 @@ _SIGS = {
     "gpr_optimize": ([_vp, _vp, _i64, _i64, _i64, _int, ctypes.POINTER(_dbl), ctypes.POINTER(_int), _int, _dbl, _dbl,
                       _dbl, _dbl, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _vp, _vp, _sz, _vp], _int),
     "gpr_cholesky_census": ([_i64, ctypes.POINTER(_i64)], _int),
+    "gpr_cholesky_schedule_check": ([_i64, _i64, _int, _i64, ctypes.POINTER(_i64)], _int),
     "gpr_timing_enable": ([_int], _int),
     "gpr_split_bf16x3": ([_vp, _i64, _vp, _vp, _vp, _vp], _int),
     "gpr_stats_workspace": ([_i64, ctypes.POINTER(_sz)], _int),
@@ -192,6 +193,16 @@ def gpr_cholesky_census(T):
     c = (_i64 * 4)()
     _check(load().gpr_cholesky_census(T, c))
     return dict(potrf=c[0], trsm=c[1], syrk=c[2], gemm=c[3])
+
+
+SCHEDULE_REPORT = ("launches", "launches_main", "launches_aux", "waits", "concurrent_pairs", "conflicts",
+                   "unannotated", "early_waits")
+
+
+def gpr_cholesky_schedule_check(n, tile, prec, omit_event=-1):
+    r = (_i64 * 8)()
+    _check(load().gpr_cholesky_schedule_check(n, tile, _prec(prec), omit_event, r))
+    return dict(zip(SCHEDULE_REPORT, list(r)))
 
 
 def gpr_timing_enable(on: bool):

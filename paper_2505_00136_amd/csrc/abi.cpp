@@ -220,11 +220,12 @@ void describe_diag(Program& P, const TileLayout& L, void* K, const CholWs& w, in
   const int64_t b = L.b;
   double* Dk = L.diag(K, k);
   double* Wk = L.winv(K, k);
-  P.kernel([=](hipStream_t s) { return launch_set_identity(Wk, b, s); });
+  P.kernel([=](hipStream_t s) { return launch_set_identity(Wk, b, s); }, {}, {span(Wk, b * b * 8)});
   const int64_t nbk = kInnerBlock;
   for (int64_t r0 = 0; r0 < b; r0 += nbk) {
     const int64_t jb = std::min(nbk, b - r0), rb = r0 + jb, nbelow = b - rb;
-    P.kernel([=](hipStream_t s) { return launch_potrf_block(Dk + r0 * b + r0, b, Wk + r0 * b + r0, b, (int)jb, k * b + r0, w.info, s); });
+    P.kernel([=](hipStream_t s) { return launch_potrf_block(Dk + r0 * b + r0, b, Wk + r0 * b + r0, b, (int)jb, k * b + r0, w.info, s); },
+             {}, {span2d(Dk + r0 * b + r0, jb, jb, b, 8), span2d(Wk + r0 * b + r0, jb, jb, b, 8), span(w.info, 8)});
     P.gemm_begin(0);
     // block row j of W: W_j[:, 0:r0] <- W_jj W_j[:, 0:r0]  (in place, column-partitioned)
     P.job(Wk + r0 * b, b, nullptr, 0, jb, r0, 1.0, 0.0, 0);
@@ -244,7 +245,7 @@ void describe_diag(Program& P, const TileLayout& L, void* K, const CholWs& w, in
       P.gemm_end();
     }
   }
-  P.kernel([=](hipStream_t s) { return launch_zero_upper(Dk, b, s); });
+  P.kernel([=](hipStream_t s) { return launch_zero_upper(Dk, b, s); }, {}, {span(Dk, b * b * 8)});
 }
 
 // Inputs of the TRSM of panel k (block column k below the diagonal): a copy of the panel
@@ -254,10 +255,12 @@ void describe_panel_copy(Program& P, const TileLayout& L, void* K, int prec, con
   if (k >= T - 1) return;
   const void* panel = L.off(K, k + 1, k);
   const size_t pbytes = (size_t)(T - k - 1) * b * b * L.esize;
-  P.kernel([=](hipStream_t s) { return launch_copy(w.panel, panel, pbytes, s); });
+  P.kernel([=](hipStream_t s) { return launch_copy(w.panel, panel, pbytes, s); }, {span(panel, pbytes)},
+           {span(w.panel, pbytes)});
   if (is_mixed(prec)) {
     const double* Wk = L.winv(K, k);
-    P.kernel([=](hipStream_t s) { return launch_convert_f64_f32(Wk, w.w32, b * b, s); });
+    P.kernel([=](hipStream_t s) { return launch_convert_f64_f32(Wk, w.w32, b * b, s); }, {span(Wk, b * b * 8)},
+             {span(w.w32, b * b * 4)});
   }
 }
 
@@ -281,9 +284,12 @@ void describe_split(Program& P, const TileLayout& L, void* K, int prec, const Ch
   const int64_t pstride = (T - 1) * b * b, count = (T - k - 1) * b * b;
   const float* panel = (const float*)L.off(K, k + 1, k);
   uint16_t* pl = w.planes + (k & 1) * 3 * pstride;
+  const int np = prec == GPR_BF16X6 ? 3 : 2;
+  std::vector<Span> wr;
+  for (int p = 0; p < np; ++p) wr.push_back(span(pl + p * pstride, count * 2));
   P.kernel([=](hipStream_t s) {
     return launch_split_bf16x3(panel, count, pl, pl + pstride, prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr, s);
-  });
+  }, {span(panel, count * 4)}, wr);
 }
 
 // Trailing update of step k restricted to block columns [n0, n1) (SYRK on diagonal tiles,
@@ -374,7 +380,7 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
   auto e2 = [](int64_t k) { return 2 + 2 * (int)k; };
   unsigned long long* info = w.info;
   P.on(0);
-  P.kernel([=](hipStream_t s) { return launch_fill_u64(info, ~0ull, 2, s); });
+  P.kernel([=](hipStream_t s) { return launch_fill_u64(info, ~0ull, 2, s); }, {}, {span(info, 16)});
   P.record(0);
   P.on(1);
   P.wait(0);
@@ -395,7 +401,8 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
   P.wait(e2(T - 1));
   // the first failing pivot (written by atomics on the auxiliary stream), copied by a kernel
   // on the caller's stream into the slot the host reads
-  P.kernel([=](hipStream_t s) { return launch_copy(info + 2, info, 2 * sizeof(unsigned long long), s); });
+  P.kernel([=](hipStream_t s) { return launch_copy(info + 2, info, 2 * sizeof(unsigned long long), s); },
+           {span(info, 16)}, {span(info + 2, 16)});
 }
 
 struct CholSizes {
@@ -1117,6 +1124,37 @@ GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, doubl
   *launches = cnt;
   *total_ms = ms;
   *algo_flops = fl;
+  return GPR_OK;
+}
+
+GPR_API int gpr_cholesky_schedule_check(int64_t n, int64_t tile, int prec, int64_t omit_event, int64_t* report) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (!report) return fail(GPR_ERR_ARG, "report is NULL");
+  if (n == 0) {
+    for (int i = 0; i < 8; ++i) report[i] = 0;
+    return GPR_OK;
+  }
+  // symbolic addresses: the trace pass only compares them, nothing is dereferenced
+  const TileLayout L = layout_of(n, tile, prec);
+  void* K = (void*)((uintptr_t)1 << 40);
+  const size_t wsb = chol_ws_bytes(L, prec);
+  const CholWs w = carve_chol((void*)((uintptr_t)1 << 46), L, prec, wsb);
+  AccessLog log;
+  Program P;
+  P.alog = &log;
+  describe_cholesky(P, L, K, prec, w);
+  ScheduleReport r;
+  check_schedule(log, (int)omit_event, r);
+  report[0] = r.launches;
+  report[1] = r.on_stream[0];
+  report[2] = r.on_stream[1];
+  report[3] = r.waits;
+  report[4] = r.concurrent_pairs;
+  report[5] = r.conflicts;
+  report[6] = r.unannotated;
+  report[7] = r.early_waits;
   return GPR_OK;
 }
 

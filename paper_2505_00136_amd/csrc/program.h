@@ -40,6 +40,36 @@ struct TimingLog {
 };
 inline TimingLog g_timing;
 
+// Host-side access log: what each launch of a description reads and writes (byte ranges
+// [lo, hi)), and the event records and waits between the two streams.  Filled by a trace
+// pass that launches nothing; check_schedule() (schedule.cpp) uses it to show that
+// launches on different streams that touch the same bytes, one of them writing, are
+// ordered by events.
+struct Span {
+  uintptr_t lo, hi;
+};
+inline Span span(const void* p, size_t bytes) { return Span{(uintptr_t)p, (uintptr_t)p + bytes}; }
+// rows x cols elements of esize bytes at p with leading dimension ld (the covering range)
+inline Span span2d(const void* p, int64_t rows, int64_t cols, int64_t ld, int esize) {
+  if (rows <= 0 || cols <= 0) return Span{(uintptr_t)p, (uintptr_t)p};
+  return span(p, (size_t)(((rows - 1) * ld + cols) * esize));
+}
+struct AccessLog {
+  enum { LAUNCH = 0, RECORD = 1, WAIT = 2 };
+  struct Op {
+    int type, stream, ev;
+    std::vector<Span> rd, wr;
+  };
+  std::vector<Op> ops;
+  int64_t unannotated = 0;   // launches issued without access annotations
+};
+struct ScheduleReport {
+  int64_t launches = 0, on_stream[2] = {0, 0}, waits = 0, concurrent_pairs = 0, conflicts = 0, unannotated = 0,
+          early_waits = 0;
+};
+// omit_wait >= 0 analyses the schedule as if the waits on that event were missing.
+void check_schedule(const AccessLog& log, int omit_wait, ScheduleReport& rep);
+
 struct Program {
   bool exec = false;
   hipStream_t st = nullptr;        // the caller's stream
@@ -62,15 +92,18 @@ struct Program {
   // three partial sums at partial + 3 * (trace_wg + its block index)); trace_cap bounds it
   const TraceArgs* trace = nullptr;
   int64_t trace_wg = 0, trace_cap = 0;
+  AccessLog* alog = nullptr;   // trace pass: log accesses, launch nothing
 
   hipStream_t stream() const { return cur == 1 && aux ? aux : st; }
   void on(int s) { cur = s; }
   // Event ev is recorded on / waited for by the current stream (execute pass only).
   void record(int ev) {
+    if (alog) alog->ops.push_back({AccessLog::RECORD, cur, ev, {}, {}});
     if (!exec || err != hipSuccess || !events || ev >= (int)events->size()) return;
     err = hipEventRecord((*events)[ev], stream());
   }
   void wait(int ev) {
+    if (alog) alog->ops.push_back({AccessLog::WAIT, cur, ev, {}, {}});
     if (!exec || err != hipSuccess || !events || ev >= (int)events->size()) return;
     err = hipStreamWaitEvent(stream(), (*events)[ev], 0);
   }
@@ -133,6 +166,7 @@ struct Program {
   }
   void gemm_end() {
     const int nj = (int)jobs.size() - job0;
+    if (alog && nj > 0) log_gemm(nj);
     if (!exec || err != hipSuccess || nj == 0) return;
     gemm_flops_wg += nwg;
     hipEvent_t ea = nullptr, eb = nullptr;
@@ -176,9 +210,45 @@ struct Program {
     }
   }
   // Launches produced by `fn` (given the current stream) run only in the execute pass.
+  // `rd` / `wr`: the byte ranges the launch reads / writes (read-modify-write counts as a
+  // write), for the trace pass.
   void kernel(const std::function<hipError_t(hipStream_t)>& fn) {
+    if (alog) {
+      alog->ops.push_back({AccessLog::LAUNCH, cur, -1, {}, {}});
+      alog->unannotated++;
+    }
     if (!exec || err != hipSuccess) return;
     err = fn(stream());
+  }
+  void kernel(const std::function<hipError_t(hipStream_t)>& fn, std::vector<Span> rd, std::vector<Span> wr) {
+    if (alog) alog->ops.push_back({AccessLog::LAUNCH, cur, -1, std::move(rd), std::move(wr)});
+    if (!exec || err != hipSuccess) return;
+    err = fn(stream());
+  }
+
+  // Access ranges of the open tile-GEMM launch: C (and Cin) of every job, the operand
+  // extents of its segments (all planes in the split modes).
+  void log_gemm(int nj) {
+    AccessLog::Op op{AccessLog::LAUNCH, cur, -1, {}, {}};
+    const bool split = kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6;
+    const int oe = split ? 2 : ((f32 || kind == GEMM_KIND_WIDEN) ? 4 : 8);
+    const int planes = kind == GEMM_KIND_BF16X6 ? 3 : (kind == GEMM_KIND_BF16X3 ? 2 : 1);
+    for (int jx = job0; jx < job0 + nj; ++jx) {
+      const GemmJob& J = jobs[jx];
+      const int ce = (J.flags & JOB_C_F32) ? 4 : 8;
+      op.wr.push_back(span2d(J.C, J.M, J.N, J.ldc, ce));
+      if (J.Cin && J.beta != 0.0) op.rd.push_back(span2d(J.Cin, J.M, J.N, J.ldcin, ce));
+      for (int sx = J.seg0; sx < J.seg0 + J.nseg; ++sx) {
+        const GemmSeg& S = segs[sx];
+        for (int p = 0; p < planes; ++p) {
+          const char* a = (const char*)S.A + (size_t)p * S.pstrideA * oe;
+          const char* bp = (const char*)S.B + (size_t)p * S.pstrideB * oe;
+          op.rd.push_back(S.modeA == MODE_KC ? span2d(a, J.M, S.K, S.lda, oe) : span2d(a, S.K, J.M, S.lda, oe));
+          op.rd.push_back(S.modeB == MODE_KC ? span2d(bp, J.N, S.K, S.ldb, oe) : span2d(bp, S.K, J.N, S.ldb, oe));
+        }
+      }
+    }
+    alog->ops.push_back(std::move(op));
   }
 };
 

@@ -70,3 +70,41 @@ def test_census_matches_fig1(lib):
     for T in (1, 4, 16, 32):
         c = lib.gpr_cholesky_census(T)
         assert c == dict(potrf=T, trsm=math.comb(T, 2), syrk=math.comb(T, 2), gemm=math.comb(T, 3))
+
+
+# ------------------------------------------------ dependency order of the two-stream schedule
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_cholesky_schedule_has_no_unordered_conflicts(lib, prec):
+    """Every pair of launches on different streams that touch common bytes (one writing)
+    is ordered by an event, for 1..24 tiles of 128 and of 256 (1 and 4 inner blocks), and
+    the look-ahead really overlaps work (concurrent pairs exist from 3 tiles on)."""
+    for b in (64, 128, 256):
+        for T in list(range(1, 13)) + [17, 24]:
+            r = lib.gpr_cholesky_schedule_check(T * b, b, prec)
+            assert r["conflicts"] == 0, (b, T, r)
+            assert r["unannotated"] == 0 and r["early_waits"] == 0, (b, T, r)
+            assert r["launches_main"] >= 1 and r["launches_aux"] >= 1
+            if T >= 3:
+                assert r["concurrent_pairs"] > 0, (b, T, r)
+            assert r["waits"] == 2 * T
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+def test_cholesky_schedule_every_wait_is_needed(lib, prec):
+    """The check is not vacuous: dropping the waits on any one event that the schedule
+    waits for leaves a conflicting pair unordered."""
+    T, b = 8, 128
+    assert lib.gpr_cholesky_schedule_check(T * b, b, prec)["conflicts"] == 0
+    waited = [0] + [2 + 2 * k for k in range(T)] + [1 + 2 * k for k in range(T - 1)]
+    for ev in waited:
+        r = lib.gpr_cholesky_schedule_check(T * b, b, prec, ev)
+        assert r["conflicts"] > 0, (ev, r)
+    # an event nobody waits for changes nothing
+    assert lib.gpr_cholesky_schedule_check(T * b, b, prec, 1 + 2 * (T - 1))["conflicts"] == 0
+
+
+def test_cholesky_schedule_check_arguments(lib):
+    assert lib.gpr_cholesky_schedule_check(0, 4, "fp64")["launches"] == 0
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_cholesky_schedule_check(100, 64, "fp64")
+    assert e.value.code == lib.GPR_ERR_SHAPE
