@@ -1,6 +1,6 @@
 """Warm-start pipeline: labels -> training -> held-out evaluation (run on one GPU).
 
-    python -m paper_2505_00136_amd.warmstart_train --train-sets 400 --heldout 100 --out DIR
+    python -m paper_2505_00136_amd.warmstart_train --train-sets 2000 --heldout 200 --out DIR
 
 Writes DIR/labels.npz (statistics and labels, extended incrementally so a long run can be
 resumed), DIR/warmstart_mlp.npz (the trained network) and DIR/report.json (per-dataset
@@ -32,6 +32,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--out", required=True)
     ap.add_argument("--skip-labels", action="store_true")
+    ap.add_argument("--labels-only", action="store_true", help="extend labels.npz and stop (resumable)")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     runner = W.Runner()
@@ -53,6 +54,9 @@ def main():
                 np.savez(lab_path, X=np.array(X), Y=np.array(Y), info=json.dumps(info))
                 log(f"[warmstart] labels {i + 1}/{args.train_sets} ({time.time() - t0:.0f} s); last D={inf['D']} "
                     f"nlml {inf['nlml0']:.1f} -> {inf['nlml']:.1f}")
+    if args.labels_only:
+        log(f"[warmstart] {len(X)} labels in {lab_path}")
+        return 0
     X, Y = np.array(X), np.array(Y)
     model, hist = W.train_model(X, Y, epochs=args.epochs, log=log)
     model.save(os.path.join(args.out, "warmstart_mlp.npz"))
