@@ -270,3 +270,30 @@ def test_autograd_function_backward(lib):
         tm = theta.detach().clone(); tm[k] -= step
         fd = (nlml(tp, gp).item() - nlml(tm, gp).item()) / (2 * step)
         assert theta.grad[k].item() == pytest.approx(fd, rel=1e-6, abs=1e-6)
+
+
+@pytest.mark.parametrize("n,tile", [(16, 1), (32, 2), (64, 4), (8, 8), (24, 3), (128, 8)])
+def test_small_problems_many_tiles(lib, n, tile):
+    """The small end of the problem-size sweep (N = M, up to 16 tiles per dimension, tiles
+    down to a single element): gradient, full covariance and two Adam steps against the
+    oracle."""
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=n, n_test=n, D=8, seed=n + tile))
+    h = Hyper(1.0, 1.0, 0.1)
+    L, a, f = oracle.fit(ds.Z, ds.y, h)
+    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, m=n)
+    assert abs(g["nlml"] - f) / abs(f) < 1e-10
+    grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    lib.gpr_nlml_grad(g["Z"], n, 8, h, g["K"], tile, "fp64", g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
+    go = oracle.nlml_grad(ds.Z, h, L, a)
+    np.testing.assert_allclose(grad.cpu().numpy(), go, rtol=1e-9, atol=1e-9 * np.max(np.abs(go)))
+    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, m=n)
+    mean, cov = _gpu_predict(lib, g, ds.Zs, h, full_cov=True)
+    assert _rel(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a)) < 1e-10
+    So = oracle.predict_var(ds.Z, ds.Zs, h, L, full_cov=True)
+    assert np.max(np.abs(cov - So)) < 1e-10 * max(1.0, np.max(np.abs(So)))
+    theta0 = [0.0, 0.0, math.log(0.1)]
+    th_o, tr_o = oracle.optimize(ds.Z, ds.y, theta0, steps=2, lr=0.1)
+    th, st, tr = lib.gpr_optimize(g["Z"], g["y"], n, 8, tile, "fp64", theta0, (1, 1, 1), 2, 0.1, 0.9, 0.999, 1e-8,
+                                  None, g["K"], g["ws"], g["wsb"])
+    np.testing.assert_allclose(th, th_o, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(tr, tr_o, rtol=1e-10)
