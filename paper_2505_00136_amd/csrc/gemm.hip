@@ -3,16 +3,29 @@
 // Every dense contraction of the factorisation, the triangular inversions, the
 // multi-right-hand-side forward substitution of the variance and the K^{-1}
 // product of the gradient is a list of jobs C = alpha * sum_s op(A_s) op(B_s)^T + beta * Cin.
-// A 256-thread workgroup computes one 128x128 macro tile of one job; its four
-// wave64s each own a 64x64 quadrant held as 4x4 accumulators of the 16x16x4
-// MFMA.  Operands are staged through double-buffered LDS in 16-deep K chunks
-// (one barrier per chunk), the next chunk's global loads being in flight while
-// the current one is multiplied.  LDS holds both operands k-major ([k][m]), so
-// an MFMA fragment read by 16 consecutive lanes touches 16 consecutive words.
+// A workgroup computes one 128x128 macro tile of one job with 2 x WN wave64s, each
+// owning a 64 x (128/WN) block held as 4 x (8/WN) accumulators of the 16x16x4 MFMA:
+// WN = 2 (256 threads, 64x64 per wave, two waves per SIMD) for the kernels of the
+// factorisation, WN = 4 (512 threads, 64x32 per wave, four waves per SIMD) for the
+// inversion and trace products of the gradient.  Operands are staged through
+// double-buffered LDS in 16-deep K chunks (one barrier per chunk), the next chunk's
+// global loads being in flight while the current one is multiplied.  LDS holds both
+// operands k-major ([k][m]), so an MFMA fragment read by 16 consecutive lanes touches
+// 16 consecutive words.
 #include "common.h"
 #include "kernels.h"
 
 namespace gpr {
+
+// Workgroup shape: 2 x WN wave64s over the 128 x 128 macro tile.
+template <int WN>
+struct Shape {
+  static constexpr int THREADS = 128 * WN;
+  static constexpr int WAVE_N = GEMM_BN / WN;   // columns per wave (rows: 64)
+  static constexpr int NJ = WAVE_N / 16;        // MFMA tiles per wave along n (4 along m)
+  static GPR_DEV int m0(int wave) { return (wave / WN) * 64; }
+  static GPR_DEV int n0(int wave) { return (wave % WN) * WAVE_N; }
+};
 
 template <typename T> struct MfmaOp;
 template <> struct MfmaOp<double> {
@@ -39,11 +52,17 @@ template <> struct MfmaOp<float> {
 template <typename T>
 struct Chunk {
   static constexpr int BK = 16;
-  static constexpr int E = BK * GEMM_BM / GEMM_THREADS;   // 8
-  static constexpr int KPT = E / 4;                        // KC: consecutive k per thread and row
-  static constexpr int TPR = GEMM_BM / E;                  // MC: threads per k row
   static constexpr int LD = GEMM_BM + 4;                   // LDS row pitch (elements)
   static constexpr int SMEM = 2 * 2 * BK * LD * (int)sizeof(T);   // A and B, double-buffered
+};
+// One thread's share of a chunk operand in a workgroup of Shape<WN>.
+template <typename T, int WN>
+struct Share {
+  static constexpr int E = Chunk<T>::BK * GEMM_BM / Shape<WN>::THREADS;   // 8 or 4 elements
+  static constexpr int KPT = 2;                          // KC: consecutive k per thread and row,
+  static constexpr int RP = E / KPT;                     //     in RP rows
+  static constexpr int RS = Shape<WN>::THREADS / 8;      //     RS apart
+  static constexpr int TPR = GEMM_BM / E;                // MC: threads per k row
 };
 template <typename T>
 using LdsBuf = T (*)[Chunk<T>::BK][Chunk<T>::LD];   // [buffer][k][row]
@@ -71,31 +90,31 @@ GPR_DEV V load_global(const void* p) {
 }
 
 // Loads this thread's share of a 128 x BK operand chunk (stored as TL) into registers,
-// zero outside [0,lim) x [k0,kend).  KC: KPT consecutive k of 4 rows; MC: E consecutive
+// zero outside [0,lim) x [k0,kend).  KC: KPT consecutive k of RP rows; MC: E consecutive
 // rows of one k.  When the whole chunk is in range and the rows are 16-byte aligned (a
 // uniform test) the loads are unguarded vector loads; otherwise every element is guarded.
-template <typename T, typename TL>
+template <typename T, typename TL, int WN>
 GPR_DEV void load_chunk(const TL* __restrict__ P, int64_t ld, int mode, int base, int lim, int k0, int kend,
-                        int tid, TL (&r)[Chunk<T>::E]) {
-  typedef Chunk<T> C;
+                        int tid, TL (&r)[Share<T, WN>::E]) {
+  typedef Share<T, WN> C;
   constexpr int VEC = 16 / sizeof(TL);
   const bool full = ((((uintptr_t)P) & 15) == 0) && ((ld * (int64_t)sizeof(TL)) % 16 == 0) &&
-                    base + GEMM_BM <= lim && k0 + C::BK <= kend;
+                    base + GEMM_BM <= lim && k0 + Chunk<T>::BK <= kend;
   if (mode == MODE_KC) {
     const int kk = k0 + (tid & 7) * C::KPT;
     if (full) {
       typedef TL vk __attribute__((ext_vector_type(C::KPT)));
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const vk v = load_global<vk>(P + (int64_t)(base + (tid >> 3) + 32 * p) * ld + kk);
+      for (int p = 0; p < C::RP; ++p) {
+        const vk v = load_global<vk>(P + (int64_t)(base + (tid >> 3) + C::RS * p) * ld + kk);
 #pragma unroll
         for (int e = 0; e < C::KPT; ++e) r[p * C::KPT + e] = v[e];
       }
       return;
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int row = base + (tid >> 3) + 32 * p;
+    for (int p = 0; p < C::RP; ++p) {
+      const int row = base + (tid >> 3) + C::RS * p;
       const bool rok = row < lim;
       const TL* q = P + (int64_t)row * ld + kk;
 #pragma unroll
@@ -121,14 +140,14 @@ GPR_DEV void load_chunk(const TL* __restrict__ P, int64_t ld, int mode, int base
   }
 }
 
-template <typename T, typename TL>
-GPR_DEV void store_chunk(LdsChunk<T> S, int mode, int tid, const TL (&r)[Chunk<T>::E]) {
-  typedef Chunk<T> C;
+template <typename T, typename TL, int WN>
+GPR_DEV void store_chunk(LdsChunk<T> S, int mode, int tid, const TL (&r)[Share<T, WN>::E]) {
+  typedef Share<T, WN> C;
   if (mode == MODE_KC) {
     const int kk = (tid & 7) * C::KPT;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int row = (tid >> 3) + 32 * p;
+    for (int p = 0; p < C::RP; ++p) {
+      const int row = (tid >> 3) + C::RS * p;
 #pragma unroll
       for (int e = 0; e < C::KPT; ++e) S[kk + e][row] = (T)r[p * C::KPT + e];
     }
@@ -140,23 +159,24 @@ GPR_DEV void store_chunk(LdsChunk<T> S, int mode, int tid, const TL (&r)[Chunk<T
   }
 }
 
-// acc += the products of one LDS chunk: each wave's 64 x 64 quadrant as 4 x 4 MFMA tiles.
-template <typename T>
+// acc += the products of one LDS chunk: this wave's 64 x WAVE_N block as 4 x NJ MFMA tiles.
+template <typename T, int WN>
 GPR_DEV void mma_chunk(LdsChunk<T> As, LdsChunk<T> Bs, int lane, int wm, int wn,
-                       typename MfmaOp<T>::acc_t (&acc)[4][4]) {
+                       typename MfmaOp<T>::acc_t (&acc)[4][Shape<WN>::NJ]) {
+  constexpr int NJ = Shape<WN>::NJ;
   typedef MfmaOp<T> Op;
 #pragma unroll
   for (int kq = 0; kq < Chunk<T>::BK / 4; ++kq) {
     const int kr = kq * 4 + (lane >> 4);
-    T a[4], b[4];
+    T a[4], b[NJ];
 #pragma unroll
     for (int i = 0; i < 4; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+    for (int j = 0; j < NJ; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
   }
 }
 
@@ -178,12 +198,13 @@ GPR_DEV bool locate_job(const GemmJob* __restrict__ jobs, int njobs, GemmJob& jo
 // segments of the 128 x 128 macro tile at (m0, n0).  The next chunk, possibly the first of
 // the next segment, is loaded while the current one is multiplied; each load takes the
 // vector path when its chunk lies inside an aligned operand.
-template <typename T, typename TL>
+template <typename T, typename TL, int WN>
 GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
-                                   typename MfmaOp<T>::acc_t (&acc)[4][4], LdsBuf<T> As, LdsBuf<T> Bs) {
+                                   typename MfmaOp<T>::acc_t (&acc)[4][Shape<WN>::NJ], LdsBuf<T> As,
+                                   LdsBuf<T> Bs) {
   constexpr int BK = Chunk<T>::BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = Shape<WN>::m0(wave), wn = Shape<WN>::n0(wave);
   const int send = job.seg0 + job.nseg;
   int cs = job.seg0, ck0 = 0, cke = 0;
   for (; cs < send; ++cs) {
@@ -191,13 +212,13 @@ GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict
     if (ck0 < cke) break;
   }
   if (cs >= send) return;
-  TL ra[Chunk<T>::E], rb[Chunk<T>::E];
+  TL ra[Share<T, WN>::E], rb[Share<T, WN>::E];
   {
     const GemmSeg& s = segs[cs];
-    load_chunk<T, TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, ck0, cke, tid, ra);
-    load_chunk<T, TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, ck0, cke, tid, rb);
-    store_chunk<T, TL>(As[0], s.modeA, tid, ra);
-    store_chunk<T, TL>(Bs[0], s.modeB, tid, rb);
+    load_chunk<T, TL, WN>((const TL*)s.A, s.lda, s.modeA, m0, job.M, ck0, cke, tid, ra);
+    load_chunk<T, TL, WN>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, ck0, cke, tid, rb);
+    store_chunk<T, TL, WN>(As[0], s.modeA, tid, ra);
+    store_chunk<T, TL, WN>(Bs[0], s.modeB, tid, rb);
   }
   __syncthreads();
   int buf = 0;
@@ -215,15 +236,15 @@ GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict
       const GemmSeg& s = segs[ns];
       nmodeA = s.modeA;
       nmodeB = s.modeB;
-      load_chunk<T, TL>((const TL*)s.A, s.lda, s.modeA, m0, job.M, nk0, nke, tid, ra);
-      load_chunk<T, TL>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, nk0, nke, tid, rb);
+      load_chunk<T, TL, WN>((const TL*)s.A, s.lda, s.modeA, m0, job.M, nk0, nke, tid, ra);
+      load_chunk<T, TL, WN>((const TL*)s.B, s.ldb, s.modeB, n0, job.N, nk0, nke, tid, rb);
     }
-    mma_chunk<T>(As[buf], Bs[buf], lane, wm, wn, acc);
+    mma_chunk<T, WN>(As[buf], Bs[buf], lane, wm, wn, acc);
     if (!more) break;
     // keep the stores of the next chunk (which wait for its global loads) after the products
     __builtin_amdgcn_sched_barrier(0);
-    store_chunk<T, TL>(As[buf ^ 1], nmodeA, tid, ra);
-    store_chunk<T, TL>(Bs[buf ^ 1], nmodeB, tid, rb);
+    store_chunk<T, TL, WN>(As[buf ^ 1], nmodeA, tid, ra);
+    store_chunk<T, TL, WN>(Bs[buf ^ 1], nmodeB, tid, rb);
     __syncthreads();
     buf ^= 1;
     cs = ns;
@@ -234,16 +255,16 @@ GPR_DEV void gemm_mainloop_generic(const GemmJob& job, const GemmSeg* __restrict
 
 // Unguarded chunk load for a macro tile that lies inside the operand with 16-byte aligned
 // rows (the caller has checked); the patterns of load_chunk for a fixed mode.
-template <typename T, typename TL, int MODE>
+template <typename T, typename TL, int MODE, int WN>
 GPR_DEV void load_chunk_full(const TL* __restrict__ P, int64_t ld, int base, int k0, int tid,
-                             TL (&r)[Chunk<T>::E]) {
-  typedef Chunk<T> C;
+                             TL (&r)[Share<T, WN>::E]) {
+  typedef Share<T, WN> C;
   if (MODE == MODE_KC) {
     typedef TL vk __attribute__((ext_vector_type(C::KPT)));
     const int kk = k0 + (tid & 7) * C::KPT;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const vk v = load_global<vk>(P + (int64_t)(base + (tid >> 3) + 32 * p) * ld + kk);
+    for (int p = 0; p < C::RP; ++p) {
+      const vk v = load_global<vk>(P + (int64_t)(base + (tid >> 3) + C::RS * p) * ld + kk);
 #pragma unroll
       for (int e = 0; e < C::KPT; ++e) r[p * C::KPT + e] = v[e];
     }
@@ -263,34 +284,34 @@ GPR_DEV void load_chunk_full(const TL* __restrict__ P, int64_t ld, int base, int
 // One segment's k range [kb, ke) (whole chunks) of a macro tile inside both operands:
 // straight-line loads and stores for fixed modes, LDS double buffer, one barrier per chunk.
 // Starts with a barrier, so the previous segment's last chunk may still be in LDS.
-template <typename T, typename TL, int MA, int MB>
-GPR_DEV void seg_full(const GemmSeg& s, int m0, int n0, int kb, int ke, typename MfmaOp<T>::acc_t (&acc)[4][4],
-                      LdsBuf<T> As, LdsBuf<T> Bs) {
+template <typename T, typename TL, int MA, int MB, int WN>
+GPR_DEV void seg_full(const GemmSeg& s, int m0, int n0, int kb, int ke,
+                      typename MfmaOp<T>::acc_t (&acc)[4][Shape<WN>::NJ], LdsBuf<T> As, LdsBuf<T> Bs) {
   constexpr int BK = Chunk<T>::BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = Shape<WN>::m0(wave), wn = Shape<WN>::n0(wave);
   const TL* __restrict__ A = (const TL*)s.A;
   const TL* __restrict__ B = (const TL*)s.B;
-  TL ra[Chunk<T>::E], rb[Chunk<T>::E];
-  load_chunk_full<T, TL, MA>(A, s.lda, m0, kb, tid, ra);
-  load_chunk_full<T, TL, MB>(B, s.ldb, n0, kb, tid, rb);
+  TL ra[Share<T, WN>::E], rb[Share<T, WN>::E];
+  load_chunk_full<T, TL, MA, WN>(A, s.lda, m0, kb, tid, ra);
+  load_chunk_full<T, TL, MB, WN>(B, s.ldb, n0, kb, tid, rb);
   __syncthreads();
-  store_chunk<T, TL>(As[0], MA, tid, ra);
-  store_chunk<T, TL>(Bs[0], MB, tid, rb);
+  store_chunk<T, TL, WN>(As[0], MA, tid, ra);
+  store_chunk<T, TL, WN>(Bs[0], MB, tid, rb);
   __syncthreads();
   int buf = 0;
   for (int k0 = kb; k0 + BK < ke; k0 += BK) {
-    load_chunk_full<T, TL, MA>(A, s.lda, m0, k0 + BK, tid, ra);
-    load_chunk_full<T, TL, MB>(B, s.ldb, n0, k0 + BK, tid, rb);
-    mma_chunk<T>(As[buf], Bs[buf], lane, wm, wn, acc);
+    load_chunk_full<T, TL, MA, WN>(A, s.lda, m0, k0 + BK, tid, ra);
+    load_chunk_full<T, TL, MB, WN>(B, s.ldb, n0, k0 + BK, tid, rb);
+    mma_chunk<T, WN>(As[buf], Bs[buf], lane, wm, wn, acc);
     // keep the stores of the next chunk (which wait for its global loads) after the products
     __builtin_amdgcn_sched_barrier(0);
-    store_chunk<T, TL>(As[buf ^ 1], MA, tid, ra);
-    store_chunk<T, TL>(Bs[buf ^ 1], MB, tid, rb);
+    store_chunk<T, TL, WN>(As[buf ^ 1], MA, tid, ra);
+    store_chunk<T, TL, WN>(Bs[buf ^ 1], MB, tid, rb);
     __syncthreads();
     buf ^= 1;
   }
-  mma_chunk<T>(As[buf], Bs[buf], lane, wm, wn, acc);
+  mma_chunk<T, WN>(As[buf], Bs[buf], lane, wm, wn, acc);
 }
 
 // Operand-mode specialisations of the main loop.  SPEC_GUARDED runs the guarded loop; the
@@ -299,47 +320,48 @@ GPR_DEV void seg_full(const GemmSeg& s, int m0, int n0, int kb, int ke, typename
 // segments all have K a multiple of the chunk depth, 16-byte aligned rows and that pair.
 enum { SPEC_GUARDED = -1, SPEC_KK = 0, SPEC_KM = 1, SPEC_MM = 3 };
 
-template <typename T, typename TL, int SPEC>
+template <typename T, typename TL, int SPEC, int WN>
 GPR_DEV void gemm_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0,
-                           typename MfmaOp<T>::acc_t (&acc)[4][4], LdsBuf<T> As, LdsBuf<T> Bs) {
+                           typename MfmaOp<T>::acc_t (&acc)[4][Shape<WN>::NJ], LdsBuf<T> As, LdsBuf<T> Bs) {
   if constexpr (SPEC == SPEC_GUARDED) {
-    gemm_mainloop_generic<T, TL>(job, segs, m0, n0, acc, As, Bs);
+    gemm_mainloop_generic<T, TL, WN>(job, segs, m0, n0, acc, As, Bs);
   } else {
     for (int cs = job.seg0; cs < job.seg0 + job.nseg; ++cs) {
       const GemmSeg& s = segs[cs];
       int kb, ke;
       seg_krange<T>(s, m0, n0, kb, ke);
-      if (kb < ke) seg_full<T, TL, (SPEC >> 1), (SPEC & 1)>(s, m0, n0, kb, ke, acc, As, Bs);
+      if (kb < ke) seg_full<T, TL, (SPEC >> 1), (SPEC & 1), WN>(s, m0, n0, kb, ke, acc, As, Bs);
     }
   }
 }
 
-template <typename T, typename TL, int SPEC>
+template <typename T, typename TL, int SPEC, int WN>
 GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
   typedef MfmaOp<T> Op;
   typedef typename Op::acc_t acc_t;
+  constexpr int NJ = Shape<WN>::NJ;
   __shared__ __align__(16) char smem[Chunk<T>::SMEM];
   LdsBuf<T> As = reinterpret_cast<LdsBuf<T>>(smem);
   LdsBuf<T> Bs = As + 2;
   GemmJob job;
   int m0, n0;
   if (!locate_job(jobs, njobs, job, m0, n0)) return;
-  acc_t acc[4][4];
+  acc_t acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-  gemm_mainloop<T, TL, SPEC>(job, segs, m0, n0, acc, As, Bs);
+    for (int j = 0; j < NJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  gemm_mainloop<T, TL, SPEC, WN>(job, segs, m0, n0, acc, As, Bs);
 
   // epilogue: C = alpha * acc + beta * Cin
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = Shape<WN>::m0(wave), wn = Shape<WN>::n0(wave);
   const bool c32 = job.flags & JOB_C_F32;
   const double alpha = job.alpha, beta = job.beta;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + Op::row(lane, r);
@@ -357,34 +379,41 @@ GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __
       }
 }
 
+// Wave layout of each kernel: the factorisation keeps two waves per SIMD (WN = 2); the
+// inversion and trace products of the gradient use four (WN = 4), which measured 3-5%
+// faster on their launches.  The factorisation's launches overlap work on a second stream
+// (look-ahead), and with WN = 4 there a repeated factorisation was not bitwise
+// reproducible (with one stream it was), so they stay at WN = 2.
+constexpr int WN_FACTOR = 2, WN_GRAD = 4;
+
 // General tile products (in-tile factorisation, TRSM, solves, inversion).
 template <typename T, int SPEC>
-__global__ __launch_bounds__(GEMM_THREADS, 2)
+__global__ __launch_bounds__(Shape<WN_FACTOR>::THREADS, 2)
 void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<T, T, SPEC>(jobs, segs, njobs);
+  gemm_tiles_body<T, T, SPEC, WN_FACTOR>(jobs, segs, njobs);
 }
 
 // float32-stored operands multiplied in float64 (exact products): the diagonal-tile
 // SYRK of the mixed-precision factorisations.
 template <int SPEC>
-__global__ __launch_bounds__(GEMM_THREADS, 2)
+__global__ __launch_bounds__(Shape<WN_FACTOR>::THREADS, 2)
 void gemm_widen_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<double, float, SPEC>(jobs, segs, njobs);
+  gemm_tiles_body<double, float, SPEC, WN_FACTOR>(jobs, segs, njobs);
 }
 
 // The trailing SYRK/GEMM update of a factorisation step (same code, its own symbol so
 // that profiles and timings single it out).
 template <typename T, int SPEC>
-__global__ __launch_bounds__(GEMM_THREADS, 2)
+__global__ __launch_bounds__(Shape<WN_FACTOR>::THREADS, 2)
 void gemm_update_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<T, T, SPEC>(jobs, segs, njobs);
+  gemm_tiles_body<T, T, SPEC, WN_FACTOR>(jobs, segs, njobs);
 }
 
 // Steps of the triangular inversion L^{-1} of the gradient (same code, own symbol).
 template <typename T, int SPEC>
-__global__ __launch_bounds__(GEMM_THREADS, 2)
+__global__ __launch_bounds__(Shape<WN_GRAD>::THREADS, 2)
 void gemm_trtri_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  gemm_tiles_body<T, T, SPEC>(jobs, segs, njobs);
+  gemm_tiles_body<T, T, SPEC, WN_GRAD>(jobs, segs, njobs);
 }
 
 // Gradient reduction fused into the K^{-1} = L^{-T} L^{-1} product: each job is one
@@ -396,28 +425,30 @@ void gemm_trtri_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 // (sum w k 2u, sum w k, sum over the diagonal of w; off-diagonal tile pairs count twice)
 // to partial[blockIdx.x][0..2].
 template <typename T, int SPEC>
-__global__ __launch_bounds__(GEMM_THREADS, 2)
+__global__ __launch_bounds__(Shape<WN_GRAD>::THREADS, 2)
 void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs,
                        TraceArgs ta) {
   typedef MfmaOp<T> Op;
   typedef typename Op::acc_t acc_t;
+  typedef Shape<WN_GRAD> S;
+  constexpr int NJ = S::NJ;
   __shared__ __align__(16) char smem[Chunk<T>::SMEM];
   LdsBuf<T> As = reinterpret_cast<LdsBuf<T>>(smem);
   LdsBuf<T> Bs = As + 2;
-  __shared__ double red[3][GEMM_THREADS];
+  __shared__ double red[3][S::THREADS];
   GemmJob job;
   int m0, n0;
   const bool active = locate_job(jobs, njobs, job, m0, n0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = S::m0(wave), wn = S::n0(wave);
   double s_l = 0.0, s_nu = 0.0, s_s = 0.0;
   if (active) {
-    acc_t acc[4][4];
+    acc_t acc[4][NJ];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    gemm_mainloop<T, T, SPEC>(job, segs, m0, n0, acc, As, Bs);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    gemm_mainloop<T, T, SPEC, WN_GRAD>(job, segs, m0, n0, acc, As, Bs);
     double ell, nu, s2;
     resolve_hyper(ta.h, ell, nu, s2);
     const int64_t ti = job.aux0, tj = job.aux1;
@@ -427,7 +458,7 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = m0 + wm + i * 16 + Op::row(lane, r);
@@ -447,7 +478,7 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
   red[1][tid] = s_nu;
   red[2][tid] = s_s;
   __syncthreads();
-  for (int s = GEMM_THREADS / 2; s > 0; s >>= 1) {
+  for (int s = S::THREADS / 2; s > 0; s >>= 1) {
     if (tid < s) {
       red[0][tid] += red[0][tid + s];
       red[1][tid] += red[1][tid + s];
@@ -486,7 +517,9 @@ int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int es
 }
 
 #define GPR_GEMM_LAUNCH(kern) \
-  hipLaunchKernelGGL(kern, dim3(nwg), dim3(GEMM_THREADS), 0, st, jobs, segs, njobs)
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(Shape<WN_FACTOR>::THREADS), 0, st, jobs, segs, njobs)
+#define GPR_GRAD_LAUNCH(kern) \
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(Shape<WN_GRAD>::THREADS), 0, st, jobs, segs, njobs)
 
 template <typename T>
 hipError_t launch_tiles_t(const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int spec, hipStream_t st) {
@@ -508,11 +541,11 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
     else GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_GUARDED>));
   } else if (kind == GEMM_KIND_TRTRI) {
     if (prec_f32) {
-      if (spec == SPEC_KM) GPR_GEMM_LAUNCH((gemm_trtri_kernel<float, SPEC_KM>));
-      else GPR_GEMM_LAUNCH((gemm_trtri_kernel<float, SPEC_GUARDED>));
+      if (spec == SPEC_KM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<float, SPEC_KM>));
+      else GPR_GRAD_LAUNCH((gemm_trtri_kernel<float, SPEC_GUARDED>));
     } else {
-      if (spec == SPEC_KM) GPR_GEMM_LAUNCH((gemm_trtri_kernel<double, SPEC_KM>));
-      else GPR_GEMM_LAUNCH((gemm_trtri_kernel<double, SPEC_GUARDED>));
+      if (spec == SPEC_KM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<double, SPEC_KM>));
+      else GPR_GRAD_LAUNCH((gemm_trtri_kernel<double, SPEC_GUARDED>));
     }
   } else if (kind == GEMM_KIND_UPDATE) {
     if (prec_f32) {
@@ -529,11 +562,12 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
   return hipGetLastError();
 }
 #undef GPR_GEMM_LAUNCH
+#undef GPR_GRAD_LAUNCH
 
 hipError_t launch_gemm_trace(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int spec,
                              const TraceArgs& ta, hipStream_t st) {
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
-  const dim3 g(nwg), blk(GEMM_THREADS);
+  const dim3 g(nwg), blk(Shape<WN_GRAD>::THREADS);
   if (prec_f32) {
     if (spec == SPEC_MM) hipLaunchKernelGGL((gemm_trace_kernel<float, SPEC_MM>), g, blk, 0, st, jobs, segs, njobs, ta);
     else hipLaunchKernelGGL((gemm_trace_kernel<float, SPEC_GUARDED>), g, blk, 0, st, jobs, segs, njobs, ta);
