@@ -135,6 +135,20 @@ def test_gradient_against_central_differences(full):
     np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6 * np.max(np.abs(fd)))
 
 
+def test_gradient_bitwise_reproducible(full):
+    """The inversion and trace kernels of the gradient (eight waves per workgroup) give the
+    same bits when the factorisation and the gradient are repeated."""
+    lib = full["lib"]
+    out = []
+    for _ in range(2):
+        alpha, _ = full["fit"](H)
+        grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+        lib.gpr_nlml_grad(full["Z"], N, D, H, full["K"], TILE, "fp64", alpha, (1, 1, 1), grad, full["ws"],
+                          full["wsb"])
+        out.append(grad.cpu().numpy())
+    assert np.array_equal(out[0], out[1]), out
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
 def test_mixed_paths_within_bounds(full, prec):
     """FP32 trailing updates and the 3-way split-bfloat16 products (hi/mid/lo, six products),
