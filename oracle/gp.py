@@ -14,6 +14,15 @@ Section 4.2: K^{-1} is applied through the Cholesky factor K = L L^T, which is
 reused for mean and uncertainty; the forward substitution V = L^{-1} K_{Z,Zs}
 serves the variance without a second solve (Section 5.1).
 
+Section 6 names Matern kernels as further kernel functions without giving them; the
+oracle uses the standard half-integer members of the Matern family with the same
+length scale l and vertical scale nu (s = r / l, r the Euclidean distance):
+  nu = 1/2:  nu exp(-s)
+  nu = 3/2:  nu (1 + sqrt(3) s) exp(-sqrt(3) s)
+  nu = 5/2:  nu (1 + sqrt(5) s + 5 s^2 / 3) exp(-sqrt(5) s)
+(the smoothness is named by the kernel tag, "matern12", "matern32", "matern52"; "se"
+is the squared-exponential kernel of Eq. 2).
+
 Readings where the paper is silent (each one is listed in the design notes):
 * sigma^2 enters K only (delta by index); cross-covariances and the test prior
   carry no noise; ``add_noise`` adds sigma^2 to the predictive variance;
@@ -35,17 +44,22 @@ from scipy.linalg import lapack
 LOG2PI = math.log(2.0 * math.pi)
 
 
+KERNELS = ("se", "matern12", "matern32", "matern52")
+
+
 @dataclass(frozen=True)
 class Hyper:
-    """Kernel hyperparameters of Eq. 2: length scale l, vertical scale nu, noise variance sigma^2."""
+    """Kernel hyperparameters of Eq. 2: length scale l, vertical scale nu, noise variance
+    sigma^2, and the kernel function (squared exponential unless a Matern tag is given)."""
     lengthscale: float
     signal_var: float
     noise_var: float
+    kernel: str = "se"
 
     @staticmethod
-    def from_log(theta) -> "Hyper":
+    def from_log(theta, kernel: str = "se") -> "Hyper":
         t = np.asarray(theta, dtype=np.float64)
-        return Hyper(float(np.exp(t[0])), float(np.exp(t[1])), float(np.exp(t[2])))
+        return Hyper(float(np.exp(t[0])), float(np.exp(t[1])), float(np.exp(t[2])), kernel)
 
     def log(self) -> np.ndarray:
         return np.log(np.array([self.lengthscale, self.signal_var, self.noise_var], dtype=np.float64))
@@ -68,9 +82,49 @@ def se_cov(A: np.ndarray, B: np.ndarray, ell: float, nu: float) -> np.ndarray:
     return nu * np.exp(-sq_dist(A, B) / (2.0 * ell * ell))
 
 
+def matern_of_r2(R2: np.ndarray, ell: float, nu: float, kernel: str) -> np.ndarray:
+    """Matern kernel values from squared distances: s = sqrt(R^2) / l, the forms in the
+    module docstring."""
+    s = np.sqrt(R2) / ell
+    if kernel == "matern12":
+        return nu * np.exp(-s)
+    if kernel == "matern32":
+        q = math.sqrt(3.0) * s
+        return nu * (1.0 + q) * np.exp(-q)
+    if kernel == "matern52":
+        q = math.sqrt(5.0) * s
+        return nu * (1.0 + q + q * q / 3.0) * np.exp(-q)
+    raise ValueError(f"unknown kernel {kernel!r}")
+
+
+def cov(A: np.ndarray, B: np.ndarray, h: Hyper) -> np.ndarray:
+    """Noise-free covariance of every pair (a_i, b_j) under h's kernel function."""
+    if h.kernel == "se":
+        return se_cov(A, B, h.lengthscale, h.signal_var)
+    return matern_of_r2(sq_dist(A, B), h.lengthscale, h.signal_var, h.kernel)
+
+
+def dcov_dlog_ell(R2: np.ndarray, h: Hyper) -> np.ndarray:
+    """Derivative of the noise-free covariance with respect to log l, elementwise:
+    se: K_f R^2 / l^2; with s = r / l, matern12: nu s exp(-s); matern32: 3 nu s^2
+    exp(-sqrt(3) s); matern52: (5/3) nu s^2 (1 + sqrt(5) s) exp(-sqrt(5) s)."""
+    ell, nu = h.lengthscale, h.signal_var
+    if h.kernel == "se":
+        return nu * np.exp(-R2 / (2.0 * ell * ell)) * R2 / (ell * ell)
+    s = np.sqrt(R2) / ell
+    if h.kernel == "matern12":
+        return nu * s * np.exp(-s)
+    if h.kernel == "matern32":
+        return 3.0 * nu * s * s * np.exp(-math.sqrt(3.0) * s)
+    if h.kernel == "matern52":
+        q = math.sqrt(5.0) * s
+        return (5.0 / 3.0) * nu * s * s * (1.0 + q) * np.exp(-q)
+    raise ValueError(f"unknown kernel {h.kernel!r}")
+
+
 def train_cov(Z: np.ndarray, h: Hyper) -> np.ndarray:
     """K of Eq. 2 over all training pairs; sigma^2 on the diagonal (delta_ij, equal indices)."""
-    K = se_cov(Z, Z, h.lengthscale, h.signal_var)
+    K = cov(Z, Z, h)
     K[np.diag_indices_from(K)] += h.noise_var
     return K
 
@@ -97,7 +151,7 @@ def predict_mean(Z, Zs, h: Hyper, alpha, block: int = 4096) -> np.ndarray:
     Zs = np.asarray(Zs, dtype=np.float64)
     out = np.empty(Zs.shape[0], dtype=np.float64)
     for j0 in range(0, Zs.shape[0], block):
-        out[j0:j0 + block] = se_cov(Zs[j0:j0 + block], Z, h.lengthscale, h.signal_var) @ alpha
+        out[j0:j0 + block] = cov(Zs[j0:j0 + block], Z, h) @ alpha
     return out
 
 
@@ -108,10 +162,10 @@ def predict_var(Z, Zs, h: Hyper, L, full_cov: bool = False, add_noise: bool = Fa
     (Section 5.1); then Sigma = K_{Zs,Zs} - V^T V.  The test prior carries no
     noise (latent f); ``add_noise`` adds sigma^2 to the variances.
     """
-    Ksz = se_cov(Z, Zs, h.lengthscale, h.signal_var)
+    Ksz = cov(Z, Zs, h)
     V = sla.solve_triangular(L, Ksz, lower=True, check_finite=False)
     if full_cov:
-        S = se_cov(Zs, Zs, h.lengthscale, h.signal_var) - V.T @ V
+        S = cov(Zs, Zs, h) - V.T @ V
         if add_noise:
             S[np.diag_indices_from(S)] += h.noise_var
         return S
@@ -133,16 +187,19 @@ def nlml_grad(Z, h: Hyper, L, alpha, trainable=(1, 1, 1)) -> np.ndarray:
     dNLML/dtheta_k = 1/2 tr(K^{-1} dK/dtheta_k) - 1/2 alpha^T (dK/dtheta_k) alpha
                    = 1/2 sum_ij (K^{-1} - alpha alpha^T)_ij (dK/dtheta_k)_ij,
     with dK/dlog l = K_f o R^2 / l^2, dK/dlog nu = K_f, dK/dlog sigma^2 = sigma^2 I,
-    K_f = nu exp(-R^2/(2 l^2)).  Entries whose ``trainable`` flag is 0 are 0.
+    K_f = nu exp(-R^2/(2 l^2)) for the squared exponential; for a Matern kernel K_f is
+    that kernel and dK/dlog l is given at ``dcov_dlog_ell``.  Entries whose ``trainable``
+    flag is 0 are 0.
     """
     n = L.shape[0]
     Kinv = sla.cho_solve((L, True), np.eye(n), check_finite=False)
     W = Kinv - np.outer(alpha, alpha)
     R2 = sq_dist(Z, Z)
-    Kf = h.signal_var * np.exp(-R2 / (2.0 * h.lengthscale ** 2))
+    Kf = (h.signal_var * np.exp(-R2 / (2.0 * h.lengthscale ** 2)) if h.kernel == "se"
+          else matern_of_r2(R2, h.lengthscale, h.signal_var, h.kernel))
     g = np.zeros(3)
     if trainable[0]:
-        g[0] = 0.5 * np.sum(W * (Kf * R2 / h.lengthscale ** 2))
+        g[0] = 0.5 * np.sum(W * dcov_dlog_ell(R2, h))
     if trainable[1]:
         g[1] = 0.5 * np.sum(W * Kf)
     if trainable[2]:
@@ -178,7 +235,7 @@ def adam_step(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, trainable
     return theta, m, v
 
 
-def optimize(Z, y, theta0, steps, lr, beta1=0.9, beta2=0.999, eps=1e-8, trainable=(1, 1, 1)):
+def optimize(Z, y, theta0, steps, lr, beta1=0.9, beta2=0.999, eps=1e-8, trainable=(1, 1, 1), kernel="se"):
     """Adam on theta = log(l, nu, sigma^2) minimising the NLML (Section 4.1).
 
     Returns (theta_N, nlml_trace) where nlml_trace[i] is the NLML at theta_i,
@@ -189,12 +246,12 @@ def optimize(Z, y, theta0, steps, lr, beta1=0.9, beta2=0.999, eps=1e-8, trainabl
     v = np.zeros(3)
     trace = []
     for t in range(1, steps + 1):
-        h = Hyper.from_log(theta)
+        h = Hyper.from_log(theta, kernel)
         L, a, f = fit(Z, y, h)
         trace.append(f)
         g = nlml_grad(Z, h, L, a, trainable)
         theta, m, v = adam_step(theta, g, m, v, t, lr, beta1, beta2, eps, trainable)
-    L, a, f = fit(Z, y, Hyper.from_log(theta))
+    L, a, f = fit(Z, y, Hyper.from_log(theta, kernel))
     trace.append(f)
     return theta, np.array(trace)
 
