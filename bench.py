@@ -162,7 +162,7 @@ def run(args):
     log(f"[bench] workload {args.workload}: n={n} m={m} D={D} tile={tile}; generating data")
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=n, n_test=m, D=D, seed=wl["seed"]))
     # hyperparameters: unit signal variance, noise 0.01, lengthscale sqrt(D) so that K is dense
-    h = (math.sqrt(D), 1.0, 0.01)
+    h = (math.sqrt(D), 1.0, 0.01, args.kernel)
     Z = torch.tensor(ds.Z, device=dev)
     Zs = torch.tensor(ds.Zs, device=dev)
     y = torch.tensor(ds.y, device=dev)
@@ -284,7 +284,7 @@ def run(args):
         "dtype": "f64" if main == "fp64" else "f32",
         "data": "synthetic (seeded mass-spring-damper NFIR regressors)",
         "config": {"workload": f"{args.workload}: n_train={n}, n_test={m}, D={D}, tile={tile}, "
-                               f"SE kernel l=sqrt(D), nu=1, sigma^2=0.01", "precisions": precs},
+                               f"{args.kernel} kernel l=sqrt(D), nu=1, sigma^2=0.01", "precisions": precs},
         "roofline": {"bound": "mfma", "kernel": f"{dom} ({dk.get('role')})" if dom else None,
                      "achieved": dk.get("achieved_tflops"), "peak": dk.get("peak_tflops"),
                      "unit": "TFLOP/s", "frac": dk.get("frac"),
@@ -306,6 +306,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n65536_d128", choices=sorted(WORKLOADS))
     ap.add_argument("--precs", default="fp64,fp32,bf16x6")
+    ap.add_argument("--kernel", default="se", choices=["se", "matern12", "matern32", "matern52"],
+                    help="covariance function (the metric is quoted for the squared exponential)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter calibration) and exit")

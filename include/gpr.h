@@ -51,11 +51,27 @@ extern "C" {
 
 #define GPR_API __attribute__((visibility("default")))
 
-/* Hyperparameters of the squared-exponential kernel, Eq. 2: l, nu, sigma^2. */
+/* Covariance functions.  GPR_KERNEL_SE is the squared exponential of Eq. 2,
+ * k(r) = nu exp(-r^2 / (2 l^2)).  The Matern kernels are the further kernel functions
+ * that Section 6 names, with s = r / l:
+ *   GPR_KERNEL_MATERN12: nu exp(-s)
+ *   GPR_KERNEL_MATERN32: nu (1 + sqrt(3) s) exp(-sqrt(3) s)
+ *   GPR_KERNEL_MATERN52: nu (1 + sqrt(5) s + 5 s^2 / 3) exp(-sqrt(5) s)
+ * In every case sigma^2 is added on the diagonal of the training covariance. */
+enum gpr_kernel {
+  GPR_KERNEL_SE = 0,
+  GPR_KERNEL_MATERN12 = 1,
+  GPR_KERNEL_MATERN32 = 2,
+  GPR_KERNEL_MATERN52 = 3
+};
+
+/* Hyperparameters of Eq. 2: l, nu, sigma^2, and the covariance function (a gpr_kernel;
+ * 0, the squared exponential, when a caller zero-initialises the struct). */
 typedef struct {
   double lengthscale;
   double signal_var;
   double noise_var;
+  int32_t kernel;
 } gpr_hyper_t;
 
 enum gpr_status {
@@ -144,7 +160,9 @@ GPR_API int gpr_nlml(const void* L_tiles, int64_t n, int64_t tile, int prec, con
 /* Gradient of the NLML in log coordinates theta = log(l, nu, sigma^2) (Section 4.1):
  *   g_k = 1/2 sum_ij (K^{-1} - alpha alpha^T)_ij (dK/dtheta_k)_ij
  * with dK/dlog l = K_f o R^2 / l^2, dK/dlog nu = K_f, dK/dlog sigma^2 = sigma^2 I,
- * K_f the noise-free kernel and R^2 the squared distances, both regenerated from Z.
+ * K_f the noise-free kernel and R^2 the squared distances, both regenerated from Z
+ * (Matern kernels, s = r / l: dK/dlog l = nu s exp(-s), 3 nu s^2 exp(-sqrt(3) s) and
+ * (5/3) nu s^2 (1 + sqrt(5) s) exp(-sqrt(5) s) for 1/2, 3/2 and 5/2).
  * K^{-1} = L^{-T} L^{-1} is formed tile by tile from the factor and consumed inside
  * the reduction.  L_tiles is destroyed: region O is overwritten with the
  * strictly-lower tiles of L^{-1}.  trainable: host[3] (0 = that entry is returned as 0,
@@ -153,7 +171,8 @@ GPR_API int gpr_nlml_grad(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, 
                           int prec, const double* alpha, const int* trainable, double* grad_log, void* ws,
                           size_t ws_bytes, void* stream);
 
-/* Adam hyperparameter optimisation (Section 4.1) of theta = log(l, nu, sigma^2):
+/* Adam hyperparameter optimisation (Section 4.1) of theta = log(l, nu, sigma^2) for the
+ * covariance function `kernel` (a gpr_kernel):
  * `steps` iterations of { assemble, Cholesky, alpha, NLML, gradient, Adam update }
  * with the optimiser state on the device, then one more NLML at the final theta.
  * theta_log: host[3] in/out.  adam_state: host[7] in/out = m[3], v[3], t (zeros to
@@ -162,7 +181,7 @@ GPR_API int gpr_nlml_grad(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, 
  * gpr_tiles_bytes().  Synchronises `stream`.  Adam: m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, theta -= lr mhat / (sqrt(vhat) + eps) with bias correction;
  * entries with trainable[k] == 0 keep theta and state. */
-GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d, int64_t tile, int prec,
+GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d, int64_t tile, int prec, int kernel,
                          double* theta_log, const int* trainable, int steps, double lr, double beta1, double beta2,
                          double eps, double* adam_state, double* nlml_trace, void* K_tiles, void* ws,
                          size_t ws_bytes, void* stream);

@@ -24,8 +24,12 @@ class GprError(RuntimeError):
         self.code = code
 
 
+KERNELS = {"se": 0, "matern12": 1, "matern32": 2, "matern52": 3}
+
+
 class GprHyper(ctypes.Structure):
-    _fields_ = [("lengthscale", ctypes.c_double), ("signal_var", ctypes.c_double), ("noise_var", ctypes.c_double)]
+    _fields_ = [("lengthscale", ctypes.c_double), ("signal_var", ctypes.c_double), ("noise_var", ctypes.c_double),
+                ("kernel", ctypes.c_int32)]
 
 
 _vp, _i64, _int, _dbl, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
@@ -41,7 +45,7 @@ _SIGS = {
     "gpr_predict_var": ([_vp, _i64, _vp, _i64, _i64, GprHyper, _vp, _i64, _int, _int, _int, _vp, _vp, _sz, _vp], _int),
     "gpr_nlml": ([_vp, _i64, _i64, _int, _vp, _vp, _vp, _vp], _int),
     "gpr_nlml_grad": ([_vp, _i64, _i64, GprHyper, _vp, _i64, _int, _vp, ctypes.POINTER(_int), _vp, _vp, _sz, _vp], _int),
-    "gpr_optimize": ([_vp, _vp, _i64, _i64, _i64, _int, ctypes.POINTER(_dbl), ctypes.POINTER(_int), _int, _dbl, _dbl,
+    "gpr_optimize": ([_vp, _vp, _i64, _i64, _i64, _int, _int, ctypes.POINTER(_dbl), ctypes.POINTER(_int), _int, _dbl, _dbl,
                       _dbl, _dbl, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _vp, _vp, _sz, _vp], _int),
     "gpr_cholesky_census": ([_i64, ctypes.POINTER(_i64)], _int),
     "gpr_cholesky_schedule_check": ([_i64, _i64, _int, _i64, ctypes.POINTER(_i64)], _int),
@@ -107,13 +111,22 @@ def _stream(stream):
     return stream.cuda_stream
 
 
+def _kernel(k) -> int:
+    return KERNELS[k] if isinstance(k, str) else int(k)
+
+
 def hyper(h) -> GprHyper:
+    """(l, nu, sigma^2) or (l, nu, sigma^2, kernel), or an object with those attributes;
+    kernel is a name of KERNELS or its number (default: squared exponential)."""
     if isinstance(h, GprHyper):
         return h
     if hasattr(h, "lengthscale"):
-        return GprHyper(h.lengthscale, h.signal_var, h.noise_var)
+        return GprHyper(h.lengthscale, h.signal_var, h.noise_var, _kernel(getattr(h, "kernel", 0)))
+    if len(h) == 4:
+        l, nu, s2, k = h
+        return GprHyper(float(l), float(nu), float(s2), _kernel(k))
     l, nu, s2 = h
-    return GprHyper(float(l), float(nu), float(s2))
+    return GprHyper(float(l), float(nu), float(s2), 0)
 
 
 def _prec(p) -> int:
@@ -178,14 +191,14 @@ def gpr_nlml_grad(Z, n, d, h, L_tiles, tile, prec, alpha, trainable, grad_log, w
 
 
 def gpr_optimize(Z, y, n, d, tile, prec, theta_log, trainable, steps, lr, beta1, beta2, eps, adam_state, K_tiles,
-                 ws, ws_bytes, stream=None):
+                 ws, ws_bytes, stream=None, kernel="se"):
     """Returns (theta_log[3], adam_state[7], nlml_trace[steps+1]) as Python lists."""
     th = (_dbl * 3)(*[float(t) for t in theta_log])
     tr = (_int * 3)(*[int(t) for t in (trainable if trainable is not None else (1, 1, 1))])
     st = (_dbl * 7)(*([float(x) for x in adam_state] if adam_state is not None else [0.0] * 7))
     trace = (_dbl * (steps + 1))()
-    _check(load().gpr_optimize(_ptr(Z), _ptr(y), n, d, tile, _prec(prec), th, tr, steps, lr, beta1, beta2, eps, st,
-                               trace, _ptr(K_tiles), _ptr(ws), ws_bytes, _stream(stream)))
+    _check(load().gpr_optimize(_ptr(Z), _ptr(y), n, d, tile, _prec(prec), _kernel(kernel), th, tr, steps, lr, beta1,
+                               beta2, eps, st, trace, _ptr(K_tiles), _ptr(ws), ws_bytes, _stream(stream)))
     return list(th), list(st), list(trace)
 
 

@@ -64,10 +64,14 @@ int check_hyper(const gpr_hyper_t& h) {
   if (!std::isfinite(h.lengthscale) || !(h.lengthscale > 0.0)) return fail(GPR_ERR_ARG, "lengthscale must be finite and > 0");
   if (!std::isfinite(h.signal_var) || !(h.signal_var > 0.0)) return fail(GPR_ERR_ARG, "signal_var must be finite and > 0");
   if (!std::isfinite(h.noise_var) || h.noise_var < 0.0) return fail(GPR_ERR_ARG, "noise_var must be finite and >= 0");
+  if (h.kernel < GPR_KERNEL_SE || h.kernel > GPR_KERNEL_MATERN52) return fail(GPR_ERR_ARG, "unknown kernel %d", h.kernel);
   return GPR_OK;
 }
 
-HyperArg harg(const gpr_hyper_t& h) { return HyperArg{h.lengthscale, h.signal_var, h.noise_var, nullptr}; }
+static_assert(GPR_KERNEL_SE == KERNEL_SE && GPR_KERNEL_MATERN12 == KERNEL_M12 && GPR_KERNEL_MATERN32 == KERNEL_M32 &&
+                  GPR_KERNEL_MATERN52 == KERNEL_M52, "kernel tags of the C-ABI and the device code differ");
+
+HyperArg harg(const gpr_hyper_t& h) { return HyperArg{h.lengthscale, h.signal_var, h.noise_var, nullptr, h.kernel}; }
 
 TileLayout layout_of(int64_t n, int64_t tile, int prec) {
   TileLayout L;
@@ -951,12 +955,13 @@ GPR_API int gpr_nlml_grad(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, 
   return grad_impl(Z, d, harg(h), L_tiles, L, prec, alpha, tr, grad_log, ws, ws_bytes, st);
 }
 
-GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d, int64_t tile, int prec,
+GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d, int64_t tile, int prec, int kernel,
                          double* theta_log, const int* trainable, int steps, double lr, double beta1, double beta2,
                          double eps, double* adam_state, double* nlml_trace, void* K_tiles, void* ws,
                          size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = check_prec(prec))) return rc;
+  if (kernel < GPR_KERNEL_SE || kernel > GPR_KERNEL_MATERN52) return fail(GPR_ERR_ARG, "unknown kernel %d", kernel);
   if ((rc = check_shape(n, tile))) return rc;
   if (d < 1 || n < 1) return fail(GPR_ERR_SHAPE, "need n >= 1 and d >= 1");
   if (steps < 0 || steps > 4095) return fail(GPR_ERR_ARG, "steps must be in [0, 4095]");
@@ -983,7 +988,7 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
   const size_t ws2_bytes = ws_bytes - state;
   HIPCHK(hipMemcpyAsync(dtheta, theta_log, 3 * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(dstate, adam_state, 7 * sizeof(double), hipMemcpyHostToDevice, st));
-  const HyperArg hd{0.0, 0.0, 0.0, dtheta};
+  const HyperArg hd{0.0, 0.0, 0.0, dtheta, kernel};
   unsigned long long* dinfo = nullptr;
   Carve cs(ws2);
   for (int s = 0; s <= steps; ++s) {

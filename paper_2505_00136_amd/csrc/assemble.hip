@@ -1,4 +1,4 @@
-// Squared-exponential covariance blocks (Eq. 2), computed from LDS-staged feature blocks.
+// Covariance blocks (Eq. 2, or a Matern kernel), computed from LDS-staged feature blocks.
 //
 // A 256-thread workgroup produces a 64 x 64 block of kernel values: the 64 row
 // points and the 64 column points are staged into LDS 32 features at a time
@@ -80,7 +80,7 @@ void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, 
   sqdist_block(Z + ti * L.b * d, L.b, r0, Z + tj * L.b * d, L.b, c0, d, za, zb, r2);
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
-  const double g = -0.5 / (ell * ell);
+  const CovFn kf(h.kernel, ell, nu);
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const bool diag = ti == tj;
   double* Dt = diag ? L.diag(K, ti) : nullptr;
@@ -93,7 +93,7 @@ void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, 
     for (int j = 0; j < 4; ++j) {
       const int64_t c = c0 + tx * 4 + j;
       if (c >= L.b) continue;
-      double v = nu * exp(g * r2[i][j]);
+      double v = kf(r2[i][j]);
       if (diag) {
         if (r == c) v += s2;
         Dt[r * L.b + c] = v;
@@ -147,7 +147,7 @@ void assemble_dense_kernel(const double* __restrict__ A, int64_t rows, const dou
   sqdist_block(A, rows, r0, B, cols, c0, d, za, zb, r2);
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
-  const double g = -0.5 / (ell * ell);
+  const CovFn kf(h.kernel, ell, nu);
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -157,7 +157,7 @@ void assemble_dense_kernel(const double* __restrict__ A, int64_t rows, const dou
     for (int j = 0; j < 4; ++j) {
       const int64_t c = c0 + tx * 4 + j;
       if (c >= cols) continue;
-      double v = nu * exp(g * r2[i][j]);
+      double v = kf(r2[i][j]);
       if (add_diag && r == c) v += s2;
       if (out_f32) ((float*)out)[r * ld + c] = (float)v;
       else ((double*)out)[r * ld + c] = v;
@@ -179,7 +179,7 @@ void kmatvec_partial_kernel(const double* __restrict__ A, int64_t rows, const do
   if (cend > cols) cend = cols;
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
-  const double g = -0.5 / (ell * ell);
+  const CovFn kf(h.kernel, ell, nu);
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t c0 = cbeg; c0 < cend; c0 += KB) {
@@ -190,7 +190,7 @@ void kmatvec_partial_kernel(const double* __restrict__ A, int64_t rows, const do
       const int64_t c = c0 + tx * 4 + j;
       const double vc = (c < cend) ? v[c] : 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = fma(nu * exp(g * r2[i][j]), vc, acc[i]);
+      for (int i = 0; i < 4; ++i) acc[i] = fma(kf(r2[i][j]), vc, acc[i]);
     }
   }
 #pragma unroll

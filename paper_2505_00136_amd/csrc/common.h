@@ -15,10 +15,59 @@ namespace gpr {
 // ---------------------------------------------------------------- hyperparameters
 // Kernels receive the hyperparameters by value; when `theta_log` is non-null they
 // use exp(theta_log[0..2]) instead, so an optimisation loop can keep them on the device.
+// `kernel` selects the covariance function (KERNEL_* below).
 struct HyperArg {
   double ell, nu, s2;
   const double* theta_log;
+  int kernel;
 };
+
+// Covariance functions: the squared exponential of Eq. 2 and the half-integer Matern
+// kernels that Section 6 names as further kernel functions (s = r / l):
+//   KERNEL_M12: nu exp(-s)
+//   KERNEL_M32: nu (1 + sqrt(3) s) exp(-sqrt(3) s)
+//   KERNEL_M52: nu (1 + sqrt(5) s + 5 s^2 / 3) exp(-sqrt(5) s)
+enum { KERNEL_SE = 0, KERNEL_M12 = 1, KERNEL_M32 = 2, KERNEL_M52 = 3 };
+constexpr double SQRT3 = 1.7320508075688772935, SQRT5 = 2.2360679774997896964;
+
+// Evaluates the selected covariance function from squared distances; set up once per
+// thread (the branch is uniform over a launch).
+struct CovFn {
+  int kernel;
+  double nu, g, inv_ell;   // g = -1 / (2 l^2)
+  GPR_DEV CovFn(int k, double ell, double nu_) : kernel(k), nu(nu_), g(-0.5 / (ell * ell)), inv_ell(1.0 / ell) {}
+  GPR_DEV double operator()(double r2) const {
+    if (kernel == KERNEL_SE) return nu * exp(g * r2);
+    const double s = sqrt(r2) * inv_ell;
+    if (kernel == KERNEL_M12) return nu * exp(-s);
+    if (kernel == KERNEL_M32) {
+      const double q = SQRT3 * s;
+      return nu * (1.0 + q) * exp(-q);
+    }
+    const double q = SQRT5 * s;
+    return nu * (1.0 + q + q * q * (1.0 / 3.0)) * exp(-q);
+  }
+};
+
+// Matern value kf and its derivative with respect to log l from u = r^2 / (2 l^2)
+// (s = sqrt(2u)): M12: nu s exp(-s); M32: 3 nu s^2 exp(-sqrt(3) s);
+// M52: (5/3) nu s^2 (1 + sqrt(5) s) exp(-sqrt(5) s).
+GPR_DEV void matern_and_dlogl(int kernel, double u, double nu, double& kf, double& dl) {
+  const double s = sqrt(2.0 * u);
+  if (kernel == KERNEL_M12) {
+    const double e = nu * exp(-s);
+    kf = e;
+    dl = s * e;
+  } else if (kernel == KERNEL_M32) {
+    const double q = SQRT3 * s, e = nu * exp(-q);
+    kf = (1.0 + q) * e;
+    dl = q * q * e;
+  } else {
+    const double q = SQRT5 * s, e = nu * exp(-q);
+    kf = (1.0 + q + q * q * (1.0 / 3.0)) * e;
+    dl = q * q * (1.0 / 3.0) * (1.0 + q) * e;
+  }
+}
 
 GPR_DEV void resolve_hyper(const HyperArg& h, double& ell, double& nu, double& s2) {
   if (h.theta_log) {

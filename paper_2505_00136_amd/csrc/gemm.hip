@@ -420,8 +420,10 @@ void gemm_trtri_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 // contribution X_ki^T X_kj of block row k of X = L^{-1} to the K^{-1} tile (i, j) = (aux0,
 // aux1).  The macro tile never leaves registers; each element w (less alpha_r alpha_c when
 // the job carries JOB_TRACE_ALPHA, once per tile) is weighted with the kernel value
-// nu exp(-u) and with 2u = r^2 / l^2, u read from the tile pair's precomputed half scaled
-// squared distances, and the workgroup writes its three partial sums
+// (nu exp(-u) for the squared exponential) and with its derivative with respect to
+// log l (nu exp(-u) 2u = K_f r^2 / l^2; the Matern forms from u), u = r^2 / (2 l^2) read
+// from the tile pair's precomputed half scaled squared distances, and the workgroup
+// writes its three partial sums
 // (sum w k 2u, sum w k, sum over the diagonal of w; off-diagonal tile pairs count twice)
 // to partial[blockIdx.x][0..2].
 template <typename T, int SPEC>
@@ -467,9 +469,16 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
             const double u = U[(int64_t)row * ta.b + col];
             double w = (double)acc[i][j][r];
             if (with_alpha) w -= ta.alpha[ti * ta.b + row] * ta.alpha[tj * ta.b + col];
-            const double kf = nu * exp(-u);
-            s_l = fma(wt * w * kf, 2.0 * u, s_l);
-            s_nu = fma(wt * w, kf, s_nu);
+            if (ta.h.kernel == KERNEL_SE) {
+              const double kf = nu * exp(-u);
+              s_l = fma(wt * w * kf, 2.0 * u, s_l);
+              s_nu = fma(wt * w, kf, s_nu);
+            } else {
+              double kf, dl;
+              matern_and_dlogl(ta.h.kernel, u, nu, kf, dl);
+              s_l = fma(wt * w, dl, s_l);
+              s_nu = fma(wt * w, kf, s_nu);
+            }
             if (ti == tj && row == col) s_s += w;
           }
         }

@@ -1,7 +1,7 @@
 """Torch-facing front end: the GP object of the paper's Python API (Section 4.3) on one GPU.
 
-A ``GP`` holds the training data, the kernel hyperparameters, the trainable
-flags and the tile configuration, and offers prediction with or without
+A ``GP`` holds the training data, the kernel function and its hyperparameters, the
+trainable flags and the tile configuration, and offers prediction with or without
 uncertainty, the loss (NLML), its gradient and Adam optimisation.  torch only
 allocates device memory and supplies the current stream; every step runs in the
 HIP kernels behind the C-ABI (``_lib``).
@@ -24,7 +24,7 @@ def _dev_f64(x, device):
 class GP:
     def __init__(self, Z, y, hyper: Sequence[float] = (1.0, 1.0, 0.1), tile: int | None = None,
                  prec: str = "fp64", trainable: Sequence[int] = (1, 1, 1), device="cuda:0",
-                 refine_sweeps: int | None = None):
+                 refine_sweeps: int | None = None, kernel: str = "se"):
         self.device = torch.device(device)
         self.Z = _dev_f64(Z, self.device)
         self.y = _dev_f64(y, self.device).reshape(-1)
@@ -35,6 +35,9 @@ class GP:
         self.prec = prec
         self.trainable = tuple(int(t) for t in trainable)
         self.hyper = tuple(float(v) for v in hyper)
+        if kernel not in _lib.KERNELS:
+            raise ValueError(f"kernel must be one of {sorted(_lib.KERNELS)}")
+        self.kernel = kernel
         self.refine_sweeps = refine_sweeps if refine_sweeps is not None else (0 if prec == "fp64" else 3)
         self._K = torch.empty(_lib.gpr_tiles_bytes(self.n, self.tile, prec), dtype=torch.uint8, device=self.device)
         self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
@@ -52,16 +55,20 @@ class GP:
     def K_tiles(self):
         return self._K
 
+    @property
+    def _h(self):
+        return (*self.hyper, self.kernel)
+
     # ---------------------------------------------------------------- training-side steps
     def fit(self):
         """Assemble K (Eq. 2), factor it tile by tile and solve for alpha."""
         ws, wsb = self._workspace()
-        _lib.gpr_assemble(self.Z, self.n, self.d, self.hyper, self.tile, self.prec, self._K)
+        _lib.gpr_assemble(self.Z, self.n, self.d, self._h, self.tile, self.prec, self._K)
         info = _lib.gpr_cholesky(self._K, self.n, self.tile, self.prec, ws, wsb, want_info=True)
         if info != 0:
             raise _lib.GprError(_lib.GPR_ERR_NOT_SPD, f"covariance is not positive definite (column {info})")
         self.alpha = torch.empty(self.n, dtype=torch.float64, device=self.device)
-        _lib.gpr_solve(self._K, self.Z, self.n, self.d, self.hyper, self.tile, self.prec, self.y, self.alpha,
+        _lib.gpr_solve(self._K, self.Z, self.n, self.d, self._h, self.tile, self.prec, self.y, self.alpha,
                        self.refine_sweeps, ws, wsb)
         self._factored = True
         return self
@@ -82,7 +89,7 @@ class GP:
         self._need_factor()
         ws, wsb = self._workspace()
         g = torch.empty(3, dtype=torch.float64, device=self.device)
-        _lib.gpr_nlml_grad(self.Z, self.n, self.d, self.hyper, self._K, self.tile, self.prec, self.alpha,
+        _lib.gpr_nlml_grad(self.Z, self.n, self.d, self._h, self._K, self.tile, self.prec, self.alpha,
                            self.trainable, g, ws, wsb)
         self._factored = False
         return g
@@ -95,7 +102,7 @@ class GP:
         m = Zs.shape[0]
         ws, wsb = self._workspace(m)
         mean = torch.empty(m, dtype=torch.float64, device=self.device)
-        _lib.gpr_predict(self.Z, self.n, Zs, m, self.d, self.hyper, self.alpha, mean, ws, wsb)
+        _lib.gpr_predict(self.Z, self.n, Zs, m, self.d, self._h, self.alpha, mean, ws, wsb)
         return mean
 
     def predict_var(self, Zs, full_cov: bool = False, add_noise: bool = False) -> torch.Tensor:
@@ -105,7 +112,7 @@ class GP:
         m = Zs.shape[0]
         ws, wsb = self._workspace(m)
         out = torch.empty((m, m) if full_cov else (m,), dtype=torch.float64, device=self.device)
-        _lib.gpr_predict_var(self.Z, self.n, Zs, m, self.d, self.hyper, self._K, self.tile, self.prec, full_cov,
+        _lib.gpr_predict_var(self.Z, self.n, Zs, m, self.d, self._h, self._K, self.tile, self.prec, full_cov,
                              add_noise, out, ws, wsb)
         return out
 
@@ -120,7 +127,7 @@ class GP:
         theta = [math.log(v) for v in self.hyper]
         theta, state, trace = _lib.gpr_optimize(self.Z, self.y, self.n, self.d, self.tile, self.prec, theta,
                                                 self.trainable, steps, lr, beta1, beta2, eps, adam_state, self._K,
-                                                ws, wsb)
+                                                ws, wsb, kernel=self.kernel)
         self.hyper = tuple(math.exp(t) for t in theta)
         self.adam_state = state
         self._factored = False

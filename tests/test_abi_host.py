@@ -108,3 +108,15 @@ def test_cholesky_schedule_check_arguments(lib):
     with pytest.raises(lib.GprError) as e:
         lib.gpr_cholesky_schedule_check(100, 64, "fp64")
     assert e.value.code == lib.GPR_ERR_SHAPE
+
+
+def test_unknown_kernel_is_rejected_before_the_gpu(lib):
+    for bad in (-1, 4, 9):
+        with pytest.raises(lib.GprError) as e:
+            lib.gpr_assemble(0x1000, 16, 2, (1.0, 1.0, 0.1, bad), 4, "fp64", 0x2000, stream=0)
+        assert e.value.code == lib.GPR_ERR_ARG
+    with pytest.raises(lib.GprError) as e:
+        lib.gpr_optimize(0x1000, 0x1000, 16, 2, 4, "fp64", (0.0, 0.0, -2.0), (1, 1, 1), 1, 0.1, 0.9, 0.999, 1e-8,
+                         None, 0x2000, 0x3000, 1 << 30, stream=0, kernel=5)
+    assert e.value.code == lib.GPR_ERR_ARG
+    assert lib.hyper((1.0, 2.0, 0.5, "matern32")).kernel == 2 and lib.hyper((1.0, 2.0, 0.5)).kernel == 0
