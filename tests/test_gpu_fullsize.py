@@ -110,7 +110,7 @@ def test_variance_bounds_and_full_covariance(full):
 
 
 def test_factorisation_bitwise_reproducible(full):
-    """The factorisation runs on two streams (look-ahead); a repeat must give the same bits."""
+    """A repeated factorisation (and solve) gives the same bits."""
     alpha2, nlml2 = full["fit"](H)
     assert torch.equal(alpha2, full["alpha"]) and nlml2 == full["nlml"]
 
