@@ -117,10 +117,11 @@ GPR_API int gpr_assemble(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, i
  * step k, POTRF of the diagonal tile (float64), TRSM of the tiles below it, SYRK
  * of the later diagonal tiles and GEMM of the other trailing tiles.  On return
  * regions D and O hold L (zero strictly-upper parts in D) and region W holds the
- * inverses of the diagonal tiles of L.  Every launch goes to `stream`, in step order,
- * unless the environment variable GPR_CHOLESKY_LOOKAHEAD=1 is set.  With it, diagonal
- * tile k+1 and its panel are factored on a second stream while the rest of step k's
- * update runs.  That mode is faster but not bitwise reproducible run to run.
+ * inverses of the diagonal tiles of L.  Diagonal tile k+1 and its panel are factored
+ * on a second stream while the rest of step k's update runs on `stream` (events order
+ * the two, and the call returns with all work ordered on `stream`).  The environment
+ * variable GPR_CHOLESKY_LOOKAHEAD=0 puts every launch on `stream` instead; both
+ * schedules give the same bits.
  * info: host out, or NULL.  When non-NULL the call synchronises `stream` and stores
  * 0, or the 1-based global column of the first non-positive pivot (LAPACK
  * convention), in which case it returns GPR_ERR_NOT_SPD and the factor is unspecified.
@@ -267,8 +268,7 @@ GPR_API int gpr_cholesky_census(int64_t T, int64_t* counts);
 
 /* Dependency check of the factorisation's two-stream schedule (the task dependencies of
  * Fig. 1 as ordering between launches), host only: runs the same description that
- * gpr_cholesky executes for (n, tile, prec) with GPR_CHOLESKY_LOOKAHEAD=1 in a pass that
- * launches nothing, recording the
+ * gpr_cholesky executes for (n, tile, prec) in a pass that launches nothing, recording the
  * byte ranges each launch reads and writes and the events between the caller's stream
  * and the auxiliary stream, and replays it with vector clocks.  report[0..7] (host array
  * of 8): launches, launches on the caller's stream, on the auxiliary stream, event waits,

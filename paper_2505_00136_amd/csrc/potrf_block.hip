@@ -53,12 +53,17 @@ void potrf_block_kernel(double* __restrict__ A, int64_t lda, double* __restrict_
     const double inv = ipiv[j];
     if (cq == 0 && i > j && i < jb) ex[i & 3][i >> 2] = nextc[i] * inv;     // column j of L
     if (i == j) {                                                             // row j of W is final
+      // Only the entries c <= j are written: the others belong to column j of L, which
+      // other waves write between the same two barriers (a store of the old value there
+      // would race with them).
 #pragma unroll
       for (int q = 0; q < PQ; ++q) {
         const int c = cq + 4 * q;
-        const double v = rw[q] * inv;
-        rw[q] = c <= j ? v : rw[q];
-        ex[cq][q] = c <= j ? v : ex[cq][q];
+        if (c <= j) {
+          const double v = rw[q] * inv;
+          rw[q] = v;
+          ex[cq][q] = v;
+        }
       }
     }
     __syncthreads();
