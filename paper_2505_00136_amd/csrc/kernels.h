@@ -28,7 +28,7 @@ hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs,
 // hi/mid/lo bfloat16 parts (round to nearest even) of float32 x; lo may be null
 hipError_t launch_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, hipStream_t st);
 
-// potrf_block.hip: Cholesky + inverse of one jb x jb (jb <= 128) diagonal block by one workgroup
+// potrf_block.hip: Cholesky + inverse of one jb x jb (jb <= 64) diagonal block by one workgroup
 hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,
                               unsigned long long* info, hipStream_t st);
 
