@@ -19,6 +19,7 @@ constexpr int BF_BK = 32;                 // k per chunk (one MFMA k-step)
 constexpr int BF_PITCH = BF_BK + 8;       // bf16 elements per LDS row (80 bytes)
 
 typedef unsigned short bfraw;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 8 packed bfloat16
 
 GPR_DEV bfraw bf16_rne_bits(float x) {
   uint32_t u = __float_as_uint(x);
@@ -44,29 +45,41 @@ __global__ void split_bf16x3_kernel(const float* __restrict__ x, int64_t count, 
 }
 
 // Loads this thread's share (one row, 16 consecutive k) of a 128 x 32 chunk of one plane.
+// When the whole chunk lies inside the plane with 16-byte aligned rows (a test that is
+// uniform over the workgroup) the loads are unguarded vector loads; otherwise every
+// element is guarded.  The loads go through global-address-space pointers: generic
+// (flat) loads would also count against the LDS wait counter, so the waits for the LDS
+// fragments of the current chunk would wait for the next chunk's loads as well.
 GPR_DEV void bf_load(const bfraw* __restrict__ P, int64_t ld, int base, int lim, int k0, int kend, int tid,
-                     uint4& r0, uint4& r1) {
+                     u32x4& r0, u32x4& r1) {
+  typedef __attribute__((address_space(1))) const u32x4 gu4;
+  typedef __attribute__((address_space(1))) const bfraw gbf;
+  const bool full = ((((uintptr_t)P) & 15) == 0) && ((ld * (int64_t)sizeof(bfraw)) % 16 == 0) &&
+                    base + GEMM_BM <= lim && k0 + BF_BK <= kend;
   const int row = base + (tid >> 1);
   const int kk = k0 + (tid & 1) * 16;
   const bfraw* q = P + (int64_t)row * ld + kk;
-  if (row < lim && kk + 16 <= kend && ((((uintptr_t)q) & 15) == 0)) {
-    r0 = *(const uint4*)q;
-    r1 = *(const uint4*)(q + 8);
+  if (full) {
+    r0 = *(gu4*)q;
+    r1 = *(gu4*)(q + 8);
   } else {
     bfraw t[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = (row < lim && kk + e < kend) ? q[e] : (bfraw)0;
-    r0 = make_uint4(t[0] | (t[1] << 16), t[2] | (t[3] << 16), t[4] | (t[5] << 16), t[6] | (t[7] << 16));
-    r1 = make_uint4(t[8] | (t[9] << 16), t[10] | (t[11] << 16), t[12] | (t[13] << 16), t[14] | (t[15] << 16));
+    for (int e = 0; e < 16; ++e) t[e] = (row < lim && kk + e < kend) ? *(gbf*)(q + e) : (bfraw)0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      r0[e] = (unsigned)t[2 * e] | ((unsigned)t[2 * e + 1] << 16);
+      r1[e] = (unsigned)t[8 + 2 * e] | ((unsigned)t[8 + 2 * e + 1] << 16);
+    }
   }
 }
 
 template <int NPLANES>
-GPR_DEV void bf_store(bfraw* S, int tid, const uint4 (&r)[NPLANES][2]) {
+GPR_DEV void bf_store(bfraw* S, int tid, const u32x4 (&r)[NPLANES][2]) {
   const int row = tid >> 1, kk = (tid & 1) * 16;
 #pragma unroll
   for (int p = 0; p < NPLANES; ++p) {
-    uint4* d = (uint4*)(S + (p * GEMM_BM + row) * BF_PITCH + kk);
+    u32x4* d = (u32x4*)(S + (p * GEMM_BM + row) * BF_PITCH + kk);
     d[0] = r[p][0];
     d[1] = r[p][1];
   }
@@ -105,22 +118,40 @@ void gemm_bf16x_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  for (int s = job.seg0; s < job.seg0 + job.nseg; ++s) {
-    const GemmSeg sg = segs[s];
-    const bfraw* A = (const bfraw*)sg.A;
-    const bfraw* B = (const bfraw*)sg.B;
-    for (int k0 = 0; k0 < sg.K; k0 += BF_BK) {
-      uint4 ra[NP][2], rb[NP][2];
+  // Chunks (segment, k0) in order; the next chunk's planes are loaded into registers
+  // while the current one is multiplied from LDS (two barriers per chunk; the planes of
+  // one chunk take 60 KB of LDS, so two workgroups share a CU).
+  const int send = job.seg0 + job.nseg;
+  int s = job.seg0;
+  while (s < send && segs[s].K <= 0) ++s;
+  if (s < send) {
+    const int koff = (lane >> 4) * 8;
+    u32x4 ra[NP][2], rb[NP][2];
+    int k0 = 0;
+    auto load = [&](int si, int kk) {
+      const GemmSeg& sg = segs[si];
+      const bfraw* A = (const bfraw*)sg.A;
+      const bfraw* B = (const bfraw*)sg.B;
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        bf_load(A + p * sg.pstrideA, sg.lda, m0, job.M, k0, sg.K, tid, ra[p][0], ra[p][1]);
-        bf_load(B + p * sg.pstrideB, sg.ldb, n0, job.N, k0, sg.K, tid, rb[p][0], rb[p][1]);
+        bf_load(A + p * sg.pstrideA, sg.lda, m0, job.M, kk, sg.K, tid, ra[p][0], ra[p][1]);
+        bf_load(B + p * sg.pstrideB, sg.ldb, n0, job.N, kk, sg.K, tid, rb[p][0], rb[p][1]);
       }
+    };
+    load(s, k0);
+    while (true) {
       __syncthreads();   // previous chunk fully consumed
       bf_store<NP>(As, tid, ra);
       bf_store<NP>(Bs, tid, rb);
       __syncthreads();
-      const int koff = (lane >> 4) * 8;
+      int ns = s, nk0 = k0 + BF_BK;
+      if (nk0 >= segs[s].K) {
+        nk0 = 0;
+        for (ns = s + 1; ns < send && segs[ns].K <= 0; ++ns) {
+        }
+      }
+      const bool more = ns < send;
+      if (more) load(ns, nk0);
       v8bf a[4][NP];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -147,6 +178,9 @@ void gemm_bf16x_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf16(a[i][0], b[0], acc[i][j]);
       }
+      if (!more) break;
+      s = ns;
+      k0 = nk0;
     }
   }
 
