@@ -22,7 +22,7 @@ def _dev_f64(x, device):
 
 
 class GP:
-    def __init__(self, Z, y, hyper: Sequence[float] = (1.0, 1.0, 0.1), tile: int | None = None,
+    def __init__(self, Z, y, hyper: Sequence[float] = (1.0, 1.0, 0.1), tile: int | str | None = None,
                  prec: str = "fp64", trainable: Sequence[int] = (1, 1, 1), device="cuda:0",
                  refine_sweeps: int | None = None, kernel: str = "se"):
         self.device = torch.device(device)
@@ -31,6 +31,9 @@ class GP:
         self.n, self.d = self.Z.shape
         if self.y.shape[0] != self.n:
             raise ValueError("Z and y disagree on n")
+        if tile == "auto":
+            from .tile_select import select_tile
+            tile, _ = select_tile(self.n, self.d, prec, Z=self.Z)
         self.tile = int(tile) if tile else self.n
         self.prec = prec
         self.trainable = tuple(int(t) for t in trainable)

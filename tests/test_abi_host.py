@@ -120,3 +120,13 @@ def test_unknown_kernel_is_rejected_before_the_gpu(lib):
                          None, 0x2000, 0x3000, 1 << 30, stream=0, kernel=5)
     assert e.value.code == lib.GPR_ERR_ARG
     assert lib.hyper((1.0, 2.0, 0.5, "matern32")).kernel == 2 and lib.hyper((1.0, 2.0, 0.5)).kernel == 0
+
+
+def test_tile_candidates():
+    from paper_2505_00136_amd.tile_select import candidate_tiles
+    assert candidate_tiles(65536) == [1024, 2048, 4096, 8192, 65536]
+    assert candidate_tiles(4096) == [256, 512, 1024, 2048, 4096]
+    assert candidate_tiles(1000) == [1000]
+    assert candidate_tiles(8) == [8]
+    for n in (1024, 3072, 16384, 98304):
+        assert all(n % b == 0 and n // b <= 64 for b in candidate_tiles(n))

@@ -297,3 +297,22 @@ def test_small_problems_many_tiles(lib, n, tile):
                                   None, g["K"], g["ws"], g["wsb"])
     np.testing.assert_allclose(th, th_o, rtol=1e-9, atol=1e-10)
     np.testing.assert_allclose(tr, tr_o, rtol=1e-10)
+
+
+def test_automatic_tile_selection(lib, tmp_path):
+    """The selector times every candidate tile on the device and returns the fastest; a
+    GP built with tile="auto" uses a valid tile and matches the oracle."""
+    from paper_2505_00136_amd.tile_select import candidate_tiles, select_tile
+    n, d = 2048, 8
+    best, times = select_tile(n, d, "fp64", reps=1, cache_path=str(tmp_path / "tiles.json"))
+    assert set(times) == set(candidate_tiles(n)) and best == min(times, key=times.get)
+    again, _ = select_tile(n, d, "fp64", cache_path=str(tmp_path / "tiles.json"))
+    assert again == best
+    from paper_2505_00136_amd.gp import GP
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=512, n_test=16, D=4, seed=9))
+    gp = GP(ds.Z, ds.y, hyper=(1.0, 1.0, 0.05), tile="auto")
+    assert 512 % gp.tile == 0
+    gp.fit()
+    h = Hyper(1.0, 1.0, 0.05)
+    _, _, f = oracle.fit(ds.Z, ds.y, h)
+    assert float(gp.nlml().item()) == pytest.approx(f, rel=1e-10)
