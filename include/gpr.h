@@ -17,8 +17,13 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it
  *    and calls return without waiting, except where a host output is documented;
  *    those calls synchronise `stream` before returning.
- *  - `tile` is the tile edge b; n must be a multiple of b (T = n / b tiles per
- *    dimension; T = 1 is the untiled, sequential case).  n = 0 is accepted and does nothing.
+ *  - `tile` is the tile edge b, any b >= 1: T = ceil(n / b) tiles per dimension (T = 1
+ *    is the untiled, sequential case).  When b does not divide n the tiled matrix has
+ *    T b rows, and rows and columns n..Tb-1 are an identity block with a zero border,
+ *    so its factor is that of the n x n covariance bordered by the identity and every
+ *    result (alpha, NLML, gradient, posterior) is the one of the n x n problem.  Vectors
+ *    passed in and out (y, alpha) always have n entries.  n = 0 is accepted and does
+ *    nothing.
  *  - Hyperparameters (Eq. 2): lengthscale l > 0, signal_var nu > 0, noise_var sigma^2 >= 0,
  *    all finite.  sigma^2 enters K only on equal indices (the Kronecker delta of Eq. 2);
  *    cross-covariances and the test prior carry no noise.
@@ -37,7 +42,8 @@
  *            column by column: tile (i,j) has index j(T-1) - j(j-1)/2 + (i-j-1).
  *            Element type float64 for GPR_FP64, float32 for the mixed modes.
  *  Only the lower triangle of K is stored; strictly-upper parts of diagonal tiles
- *  are zero after gpr_cholesky.
+ *  are zero after gpr_cholesky.  Rows and columns n..Tb-1 (present when b does not
+ *  divide n) are the identity padding, in K and in L alike.
  */
 #ifndef GPR_H_
 #define GPR_H_
@@ -77,7 +83,7 @@ typedef struct {
 enum gpr_status {
   GPR_OK = 0,
   GPR_ERR_ARG = 1,        /* null pointer, bad precision tag, non-finite or non-positive hyperparameter */
-  GPR_ERR_SHAPE = 2,      /* n not a multiple of tile, tile < 1, negative size */
+  GPR_ERR_SHAPE = 2,      /* tile < 1, negative size */
   GPR_ERR_NOT_SPD = 3,    /* a non-positive pivot in the Cholesky factorisation */
   GPR_ERR_OOM = 4,        /* a size whose byte count overflows */
   GPR_ERR_HIP = 5,        /* a HIP runtime error */
@@ -109,7 +115,8 @@ GPR_API int gpr_workspace_size(int64_t n, int64_t m, int64_t d, int64_t tile, in
 /* Covariance assembly, Eq. 2 (Section 4.1: all pairwise combinations of feature
  * vectors; Section 4.2: tile by tile).  Writes regions D and O of K_tiles with
  * K_ij = nu exp(-|z_i - z_j|^2 / (2 l^2)) + sigma^2 [i == j], lower tiles only
- * (diagonal tiles in full).  Z: n x d float64 (read only).  K_tiles: out. */
+ * (diagonal tiles in full), and the identity padding for i or j >= n.  Z: n x d
+ * float64 (read only; rows beyond n are never read).  K_tiles: out. */
 GPR_API int gpr_assemble(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, int64_t tile, int prec,
                          void* K_tiles, void* stream);
 

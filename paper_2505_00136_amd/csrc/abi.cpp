@@ -54,7 +54,6 @@ int check_prec(int prec) {
 int check_shape(int64_t n, int64_t tile) {
   if (n < 0) return fail(GPR_ERR_SHAPE, "negative size n=%lld", (long long)n);
   if (tile < 1) return fail(GPR_ERR_SHAPE, "tile must be >= 1 (got %lld)", (long long)tile);
-  if (n % tile != 0) return fail(GPR_ERR_SHAPE, "n=%lld is not a multiple of tile=%lld", (long long)n, (long long)tile);
   if (tile > (int64_t)1 << 20 || n > (int64_t)1 << 24)
     return fail(GPR_ERR_OOM, "size too large (n=%lld, tile=%lld)", (long long)n, (long long)tile);
   return GPR_OK;
@@ -77,7 +76,7 @@ TileLayout layout_of(int64_t n, int64_t tile, int prec) {
   TileLayout L;
   L.n = n;
   L.b = tile;
-  L.T = tile > 0 ? n / tile : 0;
+  L.T = tile > 0 ? (n + tile - 1) / tile : 0;
   L.esize = esize_of(prec);
   return L;
 }
@@ -459,6 +458,7 @@ CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
 // ================================================================ triangular solves
 struct SolveWs {
   double *r, *z, *t, *partial, *kpart, *res, *dvec;
+  double* xp;   // padded solution (T b) when the tile does not divide n
 };
 
 size_t solve_partial_rows(const TileLayout& L) {
@@ -468,25 +468,31 @@ size_t solve_partial_rows(const TileLayout& L) {
 
 SolveWs carve_solve(Carve& c, const TileLayout& L) {
   SolveWs w{};
-  const int64_t n = L.n, b = L.b;
-  w.r = c.take<double>(n);
-  w.z = c.take<double>(n);
+  const int64_t n = L.n, b = L.b, npad = L.npad();
+  w.r = c.take<double>(npad);
+  w.z = c.take<double>(npad);
   w.t = c.take<double>(b);
   w.partial = c.take<double>(solve_partial_rows(L) * b);
   w.kpart = c.take<double>((size_t)ceil_div(std::max<int64_t>(n, 1), kColsPerChunk) * n);
   w.res = c.take<double>(n);
   w.dvec = c.take<double>(n);
+  w.xp = npad > n ? c.take<double>(npad) : nullptr;
   return w;
 }
 
 // x = (L L^T)^{-1} y with L in tiles; the diagonal-tile inverses turn every step into a
 // matrix-vector product.  Forward: z_j = W_jj r_j, then r_below -= L_(below,j) z_j.
 // Backward: t = z_i - L_(below,i)^T x_below, then x_i = W_ii^T t.
-int tri_solve(const TileLayout& L, const void* K, const double* y, double* x, const SolveWs& w, hipStream_t st) {
-  const int64_t b = L.b, T = L.T, n = L.n;
+// y and x have n entries; the substitutions run on T b entries, the right-hand side padded
+// with zeros (the padded solution is zero too and is dropped).
+int tri_solve(const TileLayout& L, const void* K, const double* yin, double* xout, const SolveWs& w,
+              hipStream_t st) {
+  const int64_t b = L.b, T = L.T, n = L.n, npad = L.npad();
   const int f32 = L.esize == 4;
   void* Kc = const_cast<void*>(K);
-  HIPCHK(hipMemcpyAsync(w.r, y, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double* x = npad > n ? w.xp : xout;
+  HIPCHK(launch_copy(w.r, yin, n * sizeof(double), st));
+  if (npad > n) HIPCHK(launch_fill_u64((unsigned long long*)(w.r + n), 0ull, npad - n, st));
   for (int64_t j = 0; j < T; ++j) {
     HIPCHK(launch_gemv_n(L.winv(Kc, j), 0, b, b, b, w.r + j * b, 1.0, nullptr, 0.0, w.z + j * b, st));
     if (j < T - 1) {
@@ -507,6 +513,7 @@ int tri_solve(const TileLayout& L, const void* K, const double* y, double* x, co
     HIPCHK(launch_gemv_t_partial(L.winv(Kc, i), 0, b, b, b, t, w.partial, kRowsPerChunk, st));
     HIPCHK(launch_reduce_partials(w.partial, nchb, b, 1.0, nullptr, 0.0, x + i * b, st));
   }
+  if (x != xout) HIPCHK(launch_copy(xout, x, n * sizeof(double), st));
   return GPR_OK;
 }
 
@@ -528,7 +535,7 @@ int solve_impl(const TileLayout& L, const void* K, const double* Z, int64_t d, H
 
 // ================================================================ variance
 struct VarWs {
-  void* V;         // n x m (float64, or float32 in mixed modes)
+  void* V;         // T b x m (float64, or float32 in mixed modes); rows n.. are zero
   void* tmp;       // b x m
   float* w32;      // T b x b float32 copies of the diagonal-tile inverses (mixed)
   double* partial; // column sums of squares
@@ -562,14 +569,14 @@ void describe_fullcov(Program& P, const TileLayout& L, int64_t m, int prec, cons
   const bool mixed = is_mixed(prec);
   P.gemm_begin(mixed);
   P.job(out, m, out, m, m, m, -1.0, 1.0, 0);
-  P.seg(w.V, m, MODE_MC, w.V, m, MODE_MC, L.n, 0);
+  P.seg(w.V, m, MODE_MC, w.V, m, MODE_MC, L.npad(), 0);
   P.gemm_end();
 }
 
 VarWs carve_var(Carve& c, const TileLayout& L, int64_t m, int prec) {
   VarWs w{};
   const int es = is_mixed(prec) ? 4 : 8;
-  w.V = c.take<char>((size_t)L.n * m * es);
+  w.V = c.take<char>((size_t)L.npad() * m * es);
   w.tmp = c.take<char>((size_t)L.b * m * es);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.T * L.b * L.b) : nullptr;
   w.partial = c.take<double>((size_t)ceil_div(std::max<int64_t>(L.n, 1), kRowsPerChunk) * m);
@@ -585,6 +592,7 @@ struct GradWs {
   double* partial;  // [trace workgroups][3]
   int64_t partial_wg;
   double* u;        // r^2 / (2 l^2) of every lower tile pair: T (T+1) / 2 float64 tiles
+  double* apad;     // alpha padded with zeros to T b (when the tile does not divide n)
   void* arena;
 };
 
@@ -683,6 +691,7 @@ GradWs carve_grad(Carve& c, const TileLayout& L, int prec) {
   w.partial_wg = trace_workgroups(L);
   w.partial = c.take<double>((size_t)w.partial_wg * 3 + 3);
   w.u = c.take<double>((size_t)(L.T * (L.T + 1) / 2) * L.b * L.b);
+  w.apad = L.npad() > L.n ? c.take<double>(L.npad()) : nullptr;
   w.arena = c.take<char>(0);
   return w;
 }
@@ -697,7 +706,12 @@ int grad_impl(const double* Z, int64_t d, HyperArg h, void* K, const TileLayout&
   if (mixed) HIPCHK(launch_convert_f64_f32(L.winv(K, 0), w.w32, L.T * L.b * L.b, st));
   int rc = run_program([&](Program& P) { describe_trtri(P, L, K, prec, w); }, w.arena, cap, st);
   if (rc) return rc;
-  HIPCHK(launch_halfdist_tiles(Z, d, h, L.b, L.T, w.u, st));
+  HIPCHK(launch_halfdist_tiles(Z, L.n, d, h, L.b, L.T, w.u, st));
+  if (w.apad) {
+    HIPCHK(launch_copy(w.apad, alpha, L.n * sizeof(double), st));
+    HIPCHK(launch_fill_u64((unsigned long long*)(w.apad + L.n), 0ull, L.npad() - L.n, st));
+    alpha = w.apad;
+  }
   const TraceArgs ta{w.u, alpha, h, L.b, w.partial};
   int64_t nwg = 0;
   rc = run_program(
@@ -708,7 +722,7 @@ int grad_impl(const double* Z, int64_t d, HyperArg h, void* K, const TileLayout&
       },
       w.arena, cap, st, &nwg);
   if (rc) return rc;
-  HIPCHK(launch_grad_finish(w.partial, nwg, h, tr[0], tr[1], tr[2], grad, st));
+  HIPCHK(launch_grad_finish(w.partial, nwg, h, L.npad() - L.n, tr[0], tr[1], tr[2], grad, st));
   return GPR_OK;
 }
 
@@ -922,6 +936,11 @@ GPR_API int gpr_predict_var(const double* Z, int64_t n, const double* Zs, int64_
   void* K = const_cast<void*>(L_tiles);
   if (mixed) HIPCHK(launch_convert_f64_f32(L.winv(K, 0), w.w32, L.T * L.b * L.b, st));
   HIPCHK(launch_assemble_dense(Z, n, Zs, m, d, ha, 0, w.V, m, mixed ? 1 : 0, st));
+  if (L.npad() > n) {
+    // the padding's rows of the cross-covariance are zero
+    const size_t es = mixed ? 4 : 8;
+    HIPCHK(launch_zero((char*)w.V + (size_t)n * m * es, (size_t)(L.npad() - n) * m * es, st));
+  }
   if (full_cov) HIPCHK(launch_assemble_dense(Zs, m, Zs, m, d, ha, add_noise, out, m, 0, st));
   rc = run_program(
       [&](Program& P) {
@@ -950,7 +969,7 @@ GPR_API int gpr_nlml(const void* L_tiles, int64_t n, int64_t tile, int prec, con
   }
   if (!L_tiles || !y || !alpha) return fail(GPR_ERR_ARG, "null pointer");
   const TileLayout L = layout_of(n, tile, prec);
-  HIPCHK(launch_nlml(L.diag(const_cast<void*>(L_tiles), 0), L.b, L.T, y, alpha, nlml, st));
+  HIPCHK(launch_nlml(L.diag(const_cast<void*>(L_tiles), 0), L.b, L.n, y, alpha, nlml, st));
   return GPR_OK;
 }
 
@@ -1022,7 +1041,7 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
       SolveWs sw = carve_solve(c2, L);
       if ((rc = solve_impl(L, K_tiles, Z, d, hd, y, dalpha, is_mixed(prec) ? 3 : 0, sw, st))) return rc;
     }
-    HIPCHK(launch_nlml(L.diag(K_tiles, 0), L.b, L.T, y, dalpha, dtrace + s, st));
+    HIPCHK(launch_nlml(L.diag(K_tiles, 0), L.b, L.n, y, dalpha, dtrace + s, st));
     if (s == steps) break;
     {
       Carve c2(ws2);

@@ -77,7 +77,8 @@ void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, 
   const int64_t br = blk / nbt, bc = blk % nbt;
   const int64_t r0 = br * KB, c0 = bc * KB;   // within the tile
   double r2[4][4];
-  sqdist_block(Z + ti * L.b * d, L.b, r0, Z + tj * L.b * d, L.b, c0, d, za, zb, r2);
+  const int64_t ri = L.rows_of(ti), rj = L.rows_of(tj);   // real (unpadded) rows of the two tiles
+  sqdist_block(Z + ti * L.b * d, ri, r0, Z + tj * L.b * d, rj, c0, d, za, zb, r2);
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
   const CovFn kf(h.kernel, ell, nu);
@@ -94,8 +95,9 @@ void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, 
       const int64_t c = c0 + tx * 4 + j;
       if (c >= L.b) continue;
       double v = kf(r2[i][j]);
+      if (r >= ri || c >= rj) v = 0.0;   // padding: identity block, zero border
       if (diag) {
-        if (r == c) v += s2;
+        if (r == c) v = r < ri ? v + s2 : 1.0;
         Dt[r * L.b + c] = v;
       } else if (L.esize == 8) {
         ((double*)Ot)[r * L.b + c] = v;
@@ -110,7 +112,8 @@ void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, 
 // (pair y = ti (ti+1)/2 + tj at U + y b^2): the squared distances of the gradient
 // reduction, regenerated from Z once per gradient call.
 __global__ __launch_bounds__(256)
-void halfdist_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, int64_t b, double* __restrict__ U) {
+void halfdist_tiles_kernel(const double* __restrict__ Z, int64_t n, int64_t d, HyperArg h, int64_t b,
+                           double* __restrict__ U) {
   __shared__ double za[DC][KB];
   __shared__ double zb[DC][KB];
   const int64_t nbt = (b + KB - 1) / KB;
@@ -119,7 +122,9 @@ void halfdist_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, 
   pair_of(y, ti, tj);
   const int64_t r0 = (blk / nbt) * KB, c0 = (blk % nbt) * KB;
   double r2[4][4];
-  sqdist_block(Z + ti * b * d, b, r0, Z + tj * b * d, b, c0, d, za, zb, r2);
+  // padded rows (n..Tb-1) read as zero features; the reduction gives them zero weight
+  const int64_t ri = n - ti * b < b ? n - ti * b : b, rj = n - tj * b < b ? n - tj * b : b;
+  sqdist_block(Z + ti * b * d, ri, r0, Z + tj * b * d, rj, c0, d, za, zb, r2);
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
   const double g = 0.5 / (ell * ell);
@@ -207,6 +212,7 @@ void kmatvec_partial_kernel(const double* __restrict__ A, int64_t rows, const do
 hipError_t launch_assemble_tiles(const double* Z, int64_t d, HyperArg h, const TileLayout& L, void* K,
                                  hipStream_t st) {
   if (L.T == 0) return hipSuccess;
+  if (L.n <= (L.T - 1) * L.b || L.n > L.npad()) return hipErrorInvalidValue;
   const int64_t nbt = (L.b + KB - 1) / KB;
   const int64_t blocks = nbt * nbt * (L.T * (L.T + 1) / 2);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
@@ -214,13 +220,14 @@ hipError_t launch_assemble_tiles(const double* Z, int64_t d, HyperArg h, const T
   return hipGetLastError();
 }
 
-hipError_t launch_halfdist_tiles(const double* Z, int64_t d, HyperArg h, int64_t b, int64_t T, double* U,
+hipError_t launch_halfdist_tiles(const double* Z, int64_t n, int64_t d, HyperArg h, int64_t b, int64_t T, double* U,
                                  hipStream_t st) {
   if (T == 0) return hipSuccess;
   const int64_t nbt = (b + KB - 1) / KB;
   const int64_t blocks = nbt * nbt * (T * (T + 1) / 2);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(halfdist_tiles_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Z, d, h, b, U);
+  if (n <= (T - 1) * b || n > T * b) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(halfdist_tiles_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Z, n, d, h, b, U);
   return hipGetLastError();
 }
 

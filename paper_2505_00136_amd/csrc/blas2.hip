@@ -81,12 +81,11 @@ __global__ void var_finish_kernel(const double* __restrict__ partial, int64_t nc
 }
 
 __global__ __launch_bounds__(1024)
-void nlml_kernel(const double* __restrict__ D, int64_t b, int64_t T, const double* __restrict__ y,
+void nlml_kernel(const double* __restrict__ D, int64_t b, int64_t n, const double* __restrict__ y,
                  const double* __restrict__ alpha, double* out) {
   __shared__ double red[2][1024];
   const int tid = threadIdx.x;
-  const int64_t n = b * T;
-  double sl = 0.0, sy = 0.0;
+  double sl = 0.0, sy = 0.0;   // (padded pivots, rows n and beyond, are 1: log 0)
   for (int64_t i = tid; i < n; i += 1024) {
     const int64_t k = i / b, r = i % b;
     sl += log(D[k * b * b + r * (b + 1)]);
@@ -174,9 +173,9 @@ hipError_t launch_var_finish(const double* partial, int64_t nch, int64_t cols, H
   return hipGetLastError();
 }
 
-hipError_t launch_nlml(const double* D, int64_t b, int64_t T, const double* y, const double* alpha, double* nlml,
+hipError_t launch_nlml(const double* D, int64_t b, int64_t n, const double* y, const double* alpha, double* nlml,
                        hipStream_t st) {
-  hipLaunchKernelGGL(nlml_kernel, dim3(1), dim3(1024), 0, st, D, b, T, y, alpha, nlml);
+  hipLaunchKernelGGL(nlml_kernel, dim3(1), dim3(1024), 0, st, D, b, n, y, alpha, nlml);
   return hipGetLastError();
 }
 
@@ -199,8 +198,8 @@ hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStrea
 namespace gpr {
 
 __global__ __launch_bounds__(1024)
-void grad_finish_kernel(const double* __restrict__ partial, int64_t nwg, HyperArg h, int t0, int t1, int t2,
-                        double* grad) {
+void grad_finish_kernel(const double* __restrict__ partial, int64_t nwg, HyperArg h, int64_t npadded, int t0,
+                        int t1, int t2, double* grad) {
   __shared__ double red[3][1024];
   const int tid = threadIdx.x;
   double a = 0.0, b = 0.0, c = 0.0;
@@ -224,9 +223,14 @@ void grad_finish_kernel(const double* __restrict__ partial, int64_t nwg, HyperAr
   if (tid == 0) {
     double ell, nu, s2;
     resolve_hyper(h, ell, nu, s2);
+    // A padded row p has (K^{-1})_pp = 1 and zero elsewhere in its row and column (the
+    // identity border stays exact through the factor and its inverse), zero alpha_p and
+    // distance 0 to itself: it adds nu to the nu sum, 1 to the diagonal sum, 0 to the
+    // length-scale sum.
+    const double pad = (double)npadded;
     grad[0] = t0 ? 0.5 * red[0][0] : 0.0;
-    grad[1] = t1 ? 0.5 * red[1][0] : 0.0;
-    grad[2] = t2 ? 0.5 * s2 * red[2][0] : 0.0;
+    grad[1] = t1 ? 0.5 * (red[1][0] - pad * nu) : 0.0;
+    grad[2] = t2 ? 0.5 * s2 * (red[2][0] - pad) : 0.0;
   }
 }
 
@@ -250,9 +254,9 @@ __global__ void adam3_kernel(double* theta, double* state, const double* grad, d
   }
 }
 
-hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, int t0, int t1, int t2, double* grad,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(grad_finish_kernel, dim3(1), dim3(1024), 0, st, partial, nwg, h, t0, t1, t2, grad);
+hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, int64_t npadded, int t0, int t1,
+                              int t2, double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(grad_finish_kernel, dim3(1), dim3(1024), 0, st, partial, nwg, h, npadded, t0, t1, t2, grad);
   return hipGetLastError();
 }
 

@@ -86,9 +86,16 @@ GPR_DEV void resolve_hyper(const HyperArg& h, double& ell, double& nu, double& s
 //   O: T(T-1)/2 strictly-lower tiles in column-major packed order, element type `S`
 //      (float64 for the FP64 path, float32 for the mixed paths); tile (i,j), i>j,
 //      has index j(T-1) - j(j-1)/2 + (i-j-1), so the panel below a diagonal tile is contiguous.
+// T = ceil(n / b).  When b does not divide n the matrix is padded to T b rows with an
+// identity block: rows and columns n..Tb-1 are zero except for ones on the diagonal, so
+// the factor is L of the n x n matrix bordered by that identity, its log-determinant is
+// unchanged, and solves with zero-padded right-hand sides return zero padding.
 struct TileLayout {
-  int64_t n, b, T;
+  int64_t n, b, T;   // n: number of points (rows of Z), not necessarily T b
   int esize;  // bytes per element in region O (8 or 4)
+  __host__ __device__ int64_t npad() const { return T * b; }
+  // rows of Z behind tile row k (b, except in the last, partly padded tile)
+  __host__ __device__ int64_t rows_of(int64_t k) const { return n - k * b < b ? n - k * b : b; }
   __host__ __device__ int64_t tile_elems() const { return b * b; }
   __host__ __device__ int64_t off_index(int64_t i, int64_t j) const {
     return j * (T - 1) - j * (j - 1) / 2 + (i - j - 1);

@@ -39,14 +39,17 @@ hipError_t launch_convert_f64_f32(const double* src, float* dst, int64_t count, 
 // device copy with a kernel on `st` (16-byte vectors when aligned)
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t st);
+// zero `bytes` bytes at p (4-byte aligned pointer and size) with a kernel
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
 // assemble.hip
 // Lower tiles of K (Eq. 2) into the tiled layout: region D (float64) and region O (esize 8 or 4).
 hipError_t launch_assemble_tiles(const double* Z, int64_t d, HyperArg h, const TileLayout& L, void* K,
                                  hipStream_t st);
 // Dense covariance block out[r*ld + c] = k(A_r, B_c) (+ s2 where r == c when add_diag), float64 or float32.
-// u = r^2 / (2 l^2) of every lower tile pair (T (T+1)/2 float64 b x b tiles, packed row-major)
-hipError_t launch_halfdist_tiles(const double* Z, int64_t d, HyperArg h, int64_t b, int64_t T, double* U,
+// u = r^2 / (2 l^2) of every lower tile pair (T (T+1)/2 float64 b x b tiles, packed row-major);
+// Z has n rows, (T-1) b < n <= T b, padded rows read as zero features
+hipError_t launch_halfdist_tiles(const double* Z, int64_t n, int64_t d, HyperArg h, int64_t b, int64_t T, double* U,
                                  hipStream_t st);
 hipError_t launch_assemble_dense(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
                                  HyperArg h, int add_diag, void* out, int64_t ld, int out_f32,
@@ -74,15 +77,16 @@ hipError_t launch_colsq_partial(const void* V, int v_f32, int64_t ld, int64_t ro
 // out[c] = nu (+ s2 if add_noise) - sum_ch partial[ch][c]
 hipError_t launch_var_finish(const double* partial, int64_t nch, int64_t cols, HyperArg h, int add_noise,
                              double* out, hipStream_t st);
-// nlml = 1/2 y.alpha + sum_i log L_ii + n/2 log 2 pi  (L_ii read from the diagonal tiles)
-hipError_t launch_nlml(const double* Ddiag, int64_t b, int64_t T, const double* y, const double* alpha,
+// nlml = 1/2 y.alpha + sum_i log L_ii + n/2 log 2 pi over i < n (L_ii read from the diagonal tiles)
+hipError_t launch_nlml(const double* Ddiag, int64_t b, int64_t n, const double* y, const double* alpha,
                        double* nlml, hipStream_t st);
 // r = y - (Kf alpha + s2 alpha) from partial K_f alpha sums
 hipError_t launch_residual_finish(const double* partial, int64_t nch, int64_t n, HyperArg h,
                                   const double* y, const double* alpha, double* r, hipStream_t st);
-// grad[k] = trainable[k] ? 1/2 * (s_l, s_nu, s2 * s_s)[k] : 0, from per-workgroup partials
-hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, int t0, int t1, int t2, double* grad,
-                              hipStream_t st);
+// grad[k] = trainable[k] ? 1/2 * (s_l, s_nu, s2 * s_s)[k] : 0, from per-workgroup partials;
+// npadded padded rows each added exactly nu to s_nu and 1 to s_s, which are taken off
+hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, int64_t npadded, int t0, int t1,
+                              int t2, double* grad, hipStream_t st);
 // One Adam step on theta_log[3] with state m[3], v[3], t (device), masked by trainable.
 hipError_t launch_adam3(double* theta, double* state, const double* grad, double lr, double b1, double b2,
                         double eps, int t0, int t1, int t2, hipStream_t st);

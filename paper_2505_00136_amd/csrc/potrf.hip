@@ -65,6 +65,11 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, int
     p[i] = v;
 }
 
+__global__ void zero_u32_kernel(uint32_t* p, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 // Device-to-device copies are kernels (16-, 4- or 1-byte elements by alignment), never the
 // runtime's copy: a runtime copy on one stream of data a kernel on another stream produced
 // was observed to read stale data despite the event ordering them.
@@ -94,6 +99,14 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if ((((uintptr_t)p) | bytes) & 3) return hipErrorInvalidValue;
+  const int64_t count = (int64_t)(bytes / 4);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(grid_for(count)), dim3(256), 0, st, (uint32_t*)p, count);
   return hipGetLastError();
 }
 

@@ -4,9 +4,10 @@ The tile edge b sets the task granularity of the tiled factorisation (Fig. 1): f
 tiles serialise the factorisation of the diagonal tiles, many small ones add launches.
 The best b depends on n, on the device and on the precision, so the selector times the
 covariance assembly and the factorisation for every candidate b on the device and
-returns the fastest.  Candidates are the divisors of n among the powers of two from 256
-to 8192, plus n itself (one tile, the sequential baseline of Section 5.2), limited to
-those whose buffers fit in the memory budget.  Choices are cached per (device, n, d,
+returns the fastest.  Candidates are the powers of two from 256 to 8192 below n with at
+most 64 tiles per dimension (a tile that does not divide n pads the matrix with an
+identity block to ceil(n / b) b rows), plus n itself (one tile, the sequential baseline
+of Section 5.2), limited to those whose buffers fit in the memory budget.  Choices are cached per (device, n, d,
 precision) in a JSON file.
 """
 from __future__ import annotations
@@ -22,12 +23,12 @@ CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gprat_mi355x_tiles.json
 
 
 def candidate_tiles(n: int, max_tiles_per_dim: int = 64) -> list[int]:
-    """Divisors of n among 256, 512, ..., 8192 with at most max_tiles_per_dim tiles per
-    dimension, and n itself; ascending."""
+    """256, 512, ..., 8192 below n with at most max_tiles_per_dim tiles per dimension
+    (ceil(n / b), padded when b does not divide n), and n itself; ascending."""
     cands = {n}
     b = 256
     while b <= 8192:
-        if b < n and n % b == 0 and n // b <= max_tiles_per_dim:
+        if b < n and -(-n // b) <= max_tiles_per_dim:
             cands.add(b)
         b *= 2
     return sorted(cands)

@@ -41,7 +41,7 @@ def test_version_and_sizes(lib):
 
 def test_argument_errors(lib):
     with pytest.raises(lib.GprError) as e:
-        lib.gpr_tiles_bytes(1000, 256, "fp64")
+        lib.gpr_tiles_bytes(-1000, 256, "fp64")
     assert e.value.code == lib.GPR_ERR_SHAPE
     with pytest.raises(lib.GprError) as e:
         lib.gpr_tiles_bytes(1024, 0, "fp64")
@@ -54,7 +54,7 @@ def test_argument_errors(lib):
             lib.gpr_assemble(0x1000, 16, 2, h, 4, "fp64", 0x2000, stream=0)
         assert e.value.code == lib.GPR_ERR_ARG
     with pytest.raises(lib.GprError) as e:
-        lib.gpr_assemble(0x1000, 18, 2, (1.0, 1.0, 0.1), 4, "fp64", 0x2000, stream=0)
+        lib.gpr_assemble(0x1000, -18, 2, (1.0, 1.0, 0.1), 4, "fp64", 0x2000, stream=0)
     assert e.value.code == lib.GPR_ERR_SHAPE
     with pytest.raises(lib.GprError) as e:
         lib.gpr_cholesky(0x2000, 16, 4, "fp64", 0x3000, 16, stream=0)
@@ -106,8 +106,10 @@ def test_cholesky_schedule_every_wait_is_needed(lib, prec):
 def test_cholesky_schedule_check_arguments(lib):
     assert lib.gpr_cholesky_schedule_check(0, 4, "fp64")["launches"] == 0
     with pytest.raises(lib.GprError) as e:
-        lib.gpr_cholesky_schedule_check(100, 64, "fp64")
+        lib.gpr_cholesky_schedule_check(100, 0, "fp64")
     assert e.value.code == lib.GPR_ERR_SHAPE
+    # a tile that does not divide n: the padded matrix has ceil(n / tile) tiles per dimension
+    assert lib.gpr_cholesky_schedule_check(100, 64, "fp64") == lib.gpr_cholesky_schedule_check(128, 64, "fp64")
 
 
 def test_unknown_kernel_is_rejected_before_the_gpu(lib):
@@ -126,7 +128,17 @@ def test_tile_candidates():
     from paper_2505_00136_amd.tile_select import candidate_tiles
     assert candidate_tiles(65536) == [1024, 2048, 4096, 8192, 65536]
     assert candidate_tiles(4096) == [256, 512, 1024, 2048, 4096]
-    assert candidate_tiles(1000) == [1000]
+    assert candidate_tiles(1000) == [256, 512, 1000]
     assert candidate_tiles(8) == [8]
-    for n in (1024, 3072, 16384, 98304):
-        assert all(n % b == 0 and n // b <= 64 for b in candidate_tiles(n))
+    assert candidate_tiles(50000) == [1024, 2048, 4096, 8192, 50000]
+    for n in (1024, 3072, 16384, 98304, 12345):
+        assert all(b == n or (b < n and -(-n // b) <= 64) for b in candidate_tiles(n))
+
+
+def test_padded_sizes(lib):
+    """A tile that does not divide n pads the matrix to T = ceil(n / tile) tiles."""
+    for n, b in [(1000, 256), (77, 128), (300, 100), (1, 64)]:
+        T = -(-n // b)
+        for prec, es in (("fp64", 8), ("fp32", 4)):
+            assert lib.gpr_tiles_bytes(n, b, prec) == 2 * T * b * b * 8 + T * (T - 1) // 2 * b * b * es
+        assert lib.gpr_workspace_size(n, 16, 3, b, "fp64") > 0

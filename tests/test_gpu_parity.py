@@ -311,7 +311,7 @@ def test_automatic_tile_selection(lib, tmp_path):
     from paper_2505_00136_amd.gp import GP
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=512, n_test=16, D=4, seed=9))
     gp = GP(ds.Z, ds.y, hyper=(1.0, 1.0, 0.05), tile="auto")
-    assert 512 % gp.tile == 0
+    assert gp.tile in candidate_tiles(512)
     gp.fit()
     h = Hyper(1.0, 1.0, 0.05)
     _, _, f = oracle.fit(ds.Z, ds.y, h)

@@ -3,9 +3,10 @@ import numpy as np
 
 
 def tiles_to_dense_lower(raw: np.ndarray, n: int, b: int, esize: int) -> np.ndarray:
-    """Dense n x n lower matrix from the bytes of a K_tiles buffer (regions D and O)."""
-    T = n // b
-    L = np.zeros((n, n), dtype=np.float64)
+    """Dense lower matrix of T b rows, T = ceil(n / b), from the bytes of a K_tiles buffer
+    (regions D and O); n x n when b divides n, else including the identity padding."""
+    T = -(-n // b)
+    L = np.zeros((T * b, T * b), dtype=np.float64)
     dreg = raw[: T * b * b * 8].view(np.float64)
     for k in range(T):
         L[k * b:(k + 1) * b, k * b:(k + 1) * b] = np.tril(dreg[k * b * b:(k + 1) * b * b].reshape(b, b))
@@ -20,7 +21,7 @@ def tiles_to_dense_lower(raw: np.ndarray, n: int, b: int, esize: int) -> np.ndar
 
 
 def winv_tiles(raw: np.ndarray, n: int, b: int):
-    T = n // b
+    T = -(-n // b)
     wreg = raw[T * b * b * 8: 2 * T * b * b * 8].view(np.float64)
     return [wreg[k * b * b:(k + 1) * b * b].reshape(b, b) for k in range(T)]
 
@@ -32,7 +33,7 @@ def diag_tile_offset_bytes(k: int, b: int) -> int:
 def lower_row(buf, n: int, b: int, esize: int, i: int) -> np.ndarray:
     """Row i (entries 0..i) of the lower factor held in a K_tiles buffer, reading only that
     row's bytes; `buf` is the buffer as a flat uint8 torch tensor (device or host)."""
-    T = n // b
+    T = -(-n // b)
     I, r = divmod(i, b)
     parts = []
     off0 = 2 * T * b * b * 8
