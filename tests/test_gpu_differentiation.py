@@ -1,0 +1,102 @@
+"""The differentiation workload: D = 64 lagged inputs, n = 16384, measurement noise
+sigma = 0.05, 50 Adam steps (lr 0.05) on theta = log(l, nu, sigma^2) through the
+hand-written NLML backward behind a torch.autograd.Function, float32 trailing updates
+with float64 diagonal tiles and three refinement sweeps, from theta = (0, 0, log 0.1).
+
+* On an n = 512 subset the backward is checked against the oracle's analytic gradient
+  (float64 path: 1e-9; float32 path: 1e-3, the mixed-mode gradient bound) and against
+  central differences (h = 1e-5) of the oracle's NLML.
+* At n = 16384 the trajectory that torch.optim.Adam takes through the autograd Function
+  must equal the device-side Adam of gpr_optimize in the same precision (the same
+  kernels compute every NLML and gradient; only the Adam arithmetic differs, by
+  rounding), must stay within the mixed-mode bounds of the float64 trajectory (NLML
+  1e-6 relative, theta 1e-4), and must lower the NLML.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import Hyper
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N, D, TILE, SIGMA, SEED = 16384, 64, 1024, 0.05, 4
+THETA0 = (0.0, 0.0, math.log(0.1))
+STEPS, LR = 50, 0.05
+
+
+@pytest.fixture(scope="module")
+def ds():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_00136_amd import _lib
+    _lib.load()
+    return datagen.make_dataset(datagen.MSDConfig(n_train=N, n_test=8, D=D, seed=SEED, sigma_meas=SIGMA))
+
+
+@pytest.mark.parametrize("theta", [THETA0, (math.log(4.0), 0.0, math.log(0.01))])
+def test_subset_backward_against_oracle_and_central_differences(ds, theta):
+    from paper_2505_00136_amd.gp import GP, nlml
+    Z, y = ds.Z[:512], ds.y[:512]
+    h = Hyper.from_log(theta)
+    L, a, f = oracle.fit(Z, y, h)
+    go = oracle.nlml_grad(Z, h, L, a)
+    step = 1e-5
+    fd = np.zeros(3)
+    for k in range(3):
+        tp, tm = np.array(theta), np.array(theta)
+        tp[k] += step
+        tm[k] -= step
+        fd[k] = (oracle.fit(Z, y, Hyper.from_log(tp))[2] - oracle.fit(Z, y, Hyper.from_log(tm))[2]) / (2 * step)
+    scale = np.max(np.abs(go))
+    np.testing.assert_allclose(go, fd, rtol=1e-6, atol=1e-7 * scale)
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-3)):
+        gp = GP(Z, y, hyper=tuple(math.exp(v) for v in theta), tile=128, prec=prec)
+        th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+        loss = nlml(th, gp)
+        loss.backward()
+        assert loss.item() == pytest.approx(f, rel=1e-10 if prec == "fp64" else 1e-6)
+        np.testing.assert_allclose(th.grad.numpy(), go, rtol=tol, atol=tol * scale)
+        if prec == "fp64":
+            np.testing.assert_allclose(th.grad.numpy(), fd, rtol=1e-6, atol=1e-7 * scale)
+
+
+def _device_adam(ds, prec):
+    from paper_2505_00136_amd import _lib
+    dev = "cuda:0"
+    Zt, yt = torch.tensor(ds.Z, device=dev), torch.tensor(ds.y, device=dev)
+    K = torch.empty(_lib.gpr_tiles_bytes(N, TILE, prec), dtype=torch.uint8, device=dev)
+    wsb = _lib.gpr_workspace_size(N, 0, D, TILE, prec)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    th, _, tr = _lib.gpr_optimize(Zt, yt, N, D, TILE, prec, list(THETA0), (1, 1, 1), STEPS, LR, 0.9, 0.999, 1e-8,
+                                  None, K, ws, wsb)
+    return np.array(th), np.array(tr)
+
+
+def test_fifty_adam_steps_through_the_autograd_function(ds):
+    from paper_2505_00136_amd.gp import GP, nlml
+    print("[differentiation] autograd + torch.optim.Adam, float32", flush=True)
+    gp = GP(ds.Z, ds.y, hyper=tuple(math.exp(v) for v in THETA0), tile=TILE, prec="fp32")
+    theta = torch.tensor(THETA0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([theta], lr=LR, betas=(0.9, 0.999), eps=1e-8)
+    trace = []
+    for _ in range(STEPS):
+        opt.zero_grad()
+        loss = nlml(theta, gp)
+        loss.backward()
+        opt.step()
+        trace.append(loss.item())
+    trace.append(nlml(theta.detach(), gp).item())
+    trace = np.array(trace)
+    print("[differentiation] device Adam, float32 and float64", flush=True)
+    th32, tr32 = _device_adam(ds, "fp32")
+    th64, tr64 = _device_adam(ds, "fp64")
+    np.testing.assert_allclose(theta.detach().numpy(), th32, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(trace, tr32, rtol=1e-9)
+    np.testing.assert_allclose(tr32, tr64, rtol=1e-6)
+    np.testing.assert_allclose(th32, th64, rtol=0, atol=1e-4)
+    assert tr32[-1] < tr32[0] and np.all(np.isfinite(tr32))
