@@ -111,8 +111,12 @@ int upload_blob(const void* data, size_t bytes, void* dst, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_stage.mu);
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  if (g_stage.ev && g_stage.dev == dev) HIPCHK(hipEventSynchronize(g_stage.ev));
-  if (g_stage.ev && g_stage.dev != dev) g_stage.ev = nullptr;   // a new device gets its own event
+  // the previous upload (on whichever device) must have read the buffer before it is reused
+  if (g_stage.ev) HIPCHK(hipEventSynchronize(g_stage.ev));
+  if (g_stage.ev && g_stage.dev != dev) {   // a new device gets its own event
+    HIPCHK(hipEventDestroy(g_stage.ev));
+    g_stage.ev = nullptr;
+  }
   if (bytes > g_stage.cap) {
     if (g_stage.host) HIPCHK(hipHostFree(g_stage.host));
     g_stage.host = nullptr;
