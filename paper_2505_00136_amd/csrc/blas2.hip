@@ -6,6 +6,31 @@
 
 namespace gpr {
 
+// Sum over the 64 lanes of a wave (butterfly), the same value in every lane.
+GPR_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sums of two values over a 1024-thread workgroup: within each wave by shuffles, then the
+// 16 wave sums in a fixed order by the first wave.  Valid in thread 0.
+GPR_DEV void block_sum2(double& a, double& b) {
+  __shared__ double part[2][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) {
+    part[0][wave] = a;
+    part[1][wave] = b;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    a = wave_sum(lane < 16 ? part[0][lane] : 0.0);
+    b = wave_sum(lane < 16 ? part[1][lane] : 0.0);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256)
 void gemv_n_kernel(const T* __restrict__ A, int64_t lda, int64_t rows, int64_t cols, const double* __restrict__ x,
@@ -21,8 +46,7 @@ void gemv_n_kernel(const T* __restrict__ A, int64_t lda, int64_t rows, int64_t c
     s1 = fma((double)a[c + 64], x[c + 64], s1);
   }
   if (c < cols) s0 = fma((double)a[c], x[c], s0);
-  double s = s0 + s1;
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const double s = wave_sum(s0 + s1);
   if (lane == 0) {
     double v = alpha * s;
     if (beta != 0.0) v += beta * yin[r];
@@ -83,7 +107,6 @@ __global__ void var_finish_kernel(const double* __restrict__ partial, int64_t nc
 __global__ __launch_bounds__(1024)
 void nlml_kernel(const double* __restrict__ D, int64_t b, int64_t n, const double* __restrict__ y,
                  const double* __restrict__ alpha, double* out) {
-  __shared__ double red[2][1024];
   const int tid = threadIdx.x;
   double sl = 0.0, sy = 0.0;   // (padded pivots, rows n and beyond, are 1: log 0)
   for (int64_t i = tid; i < n; i += 1024) {
@@ -91,17 +114,8 @@ void nlml_kernel(const double* __restrict__ D, int64_t b, int64_t n, const doubl
     sl += log(D[k * b * b + r * (b + 1)]);
     sy = fma(y[i], alpha[i], sy);
   }
-  red[0][tid] = sl;
-  red[1][tid] = sy;
-  __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if (tid < s) {
-      red[0][tid] += red[0][tid + s];
-      red[1][tid] += red[1][tid + s];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) out[0] = 0.5 * red[1][0] + red[0][0] + 0.5 * (double)n * log(2.0 * M_PI);
+  block_sum2(sl, sy);
+  if (tid == 0) out[0] = 0.5 * sy + sl + 0.5 * (double)n * log(2.0 * M_PI);
 }
 
 __global__ void residual_finish_kernel(const double* __restrict__ partial, int64_t nch, int64_t n, HyperArg h,
@@ -200,7 +214,6 @@ namespace gpr {
 __global__ __launch_bounds__(1024)
 void grad_finish_kernel(const double* __restrict__ partial, int64_t nwg, HyperArg h, int64_t npadded, int t0,
                         int t1, int t2, double* grad) {
-  __shared__ double red[3][1024];
   const int tid = threadIdx.x;
   double a = 0.0, b = 0.0, c = 0.0;
   for (int64_t w = tid; w < nwg; w += 1024) {
@@ -208,18 +221,10 @@ void grad_finish_kernel(const double* __restrict__ partial, int64_t nwg, HyperAr
     b += partial[w * 3 + 1];
     c += partial[w * 3 + 2];
   }
-  red[0][tid] = a;
-  red[1][tid] = b;
-  red[2][tid] = c;
-  __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if (tid < s) {
-      red[0][tid] += red[0][tid + s];
-      red[1][tid] += red[1][tid + s];
-      red[2][tid] += red[2][tid + s];
-    }
-    __syncthreads();
-  }
+  block_sum2(a, b);
+  double unused = 0.0;
+  __syncthreads();   // block_sum2's wave sums are read before the next call writes them
+  block_sum2(c, unused);
   if (tid == 0) {
     double ell, nu, s2;
     resolve_hyper(h, ell, nu, s2);
@@ -228,9 +233,9 @@ void grad_finish_kernel(const double* __restrict__ partial, int64_t nwg, HyperAr
     // distance 0 to itself: it adds nu to the nu sum, 1 to the diagonal sum, 0 to the
     // length-scale sum.
     const double pad = (double)npadded;
-    grad[0] = t0 ? 0.5 * red[0][0] : 0.0;
-    grad[1] = t1 ? 0.5 * (red[1][0] - pad * nu) : 0.0;
-    grad[2] = t2 ? 0.5 * s2 * (red[2][0] - pad) : 0.0;
+    grad[0] = t0 ? 0.5 * a : 0.0;
+    grad[1] = t1 ? 0.5 * (b - pad * nu) : 0.0;
+    grad[2] = t2 ? 0.5 * s2 * (c - pad) : 0.0;
   }
 }
 
