@@ -316,3 +316,47 @@ def test_automatic_tile_selection(lib, tmp_path):
     h = Hyper(1.0, 1.0, 0.05)
     _, _, f = oracle.fit(ds.Z, ds.y, h)
     assert float(gp.nlml().item()) == pytest.approx(f, rel=1e-10)
+
+
+def test_empty_inputs(lib):
+    """n = 0: every call is a no-op or returns the prior (mean 0, variance nu, covariance
+    K(Zs, Zs)), the NLML and its gradient are 0; m = 0: the predictions touch nothing."""
+    dev = "cuda:0"
+    rng = np.random.default_rng(5)
+    m, d, tile = 17, 3, 64
+    h = Hyper(1.1, 0.7, 0.05)
+    Zs = rng.normal(size=(m, d))
+    Zst = torch.tensor(Zs, device=dev)
+    empty = torch.empty((0, d), dtype=torch.float64, device=dev)
+    e1 = torch.empty(0, dtype=torch.float64, device=dev)
+    assert lib.gpr_tiles_bytes(0, tile, "fp64") == 0
+    wsb = lib.gpr_workspace_size(0, m, d, tile, "fp64")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    K = torch.empty(0, dtype=torch.uint8, device=dev)
+    lib.gpr_assemble(empty, 0, d, h, tile, "fp64", K)
+    assert lib.gpr_cholesky(K, 0, tile, "fp64", ws, wsb) == 0
+    lib.gpr_solve(K, empty, 0, d, h, tile, "fp64", e1, e1, 0, ws, wsb)
+    nl = torch.full((1,), 7.0, dtype=torch.float64, device=dev)
+    lib.gpr_nlml(K, 0, tile, "fp64", e1, e1, nl)
+    grad = torch.full((3,), 7.0, dtype=torch.float64, device=dev)
+    lib.gpr_nlml_grad(empty, 0, d, h, K, tile, "fp64", e1, (1, 1, 1), grad, ws, wsb)
+    mean = torch.full((m,), 7.0, dtype=torch.float64, device=dev)
+    lib.gpr_predict(empty, 0, Zst, m, d, h, e1, mean, ws, wsb)
+    var = torch.empty(m, dtype=torch.float64, device=dev)
+    lib.gpr_predict_var(empty, 0, Zst, m, d, h, K, tile, "fp64", False, True, var, ws, wsb)
+    cov = torch.empty((m, m), dtype=torch.float64, device=dev)
+    lib.gpr_predict_var(empty, 0, Zst, m, d, h, K, tile, "fp64", True, False, cov, ws, wsb)
+    torch.cuda.synchronize()
+    assert nl.item() == 0.0 and torch.all(grad == 0.0) and torch.all(mean == 0.0)
+    np.testing.assert_allclose(var.cpu().numpy(), np.full(m, h.signal_var + h.noise_var), rtol=1e-15)
+    np.testing.assert_allclose(cov.cpu().numpy(), oracle.cov(Zs, Zs, h), rtol=1e-13, atol=1e-15)
+    # m = 0 with data: outputs untouched
+    n = 40
+    Z = rng.normal(size=(n, d))
+    y = np.sin(Z[:, 0])
+    g = _gpu_fit(lib, Z, y, h, 16)
+    sentinel = torch.full((4,), 3.0, dtype=torch.float64, device=dev)
+    lib.gpr_predict(g["Z"], n, Zst, 0, d, h, g["alpha"], sentinel, g["ws"], g["wsb"])
+    lib.gpr_predict_var(g["Z"], n, Zst, 0, d, h, g["K"], 16, "fp64", True, False, sentinel, g["ws"], g["wsb"])
+    torch.cuda.synchronize()
+    assert torch.all(sentinel == 3.0)
