@@ -45,10 +45,11 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gemm_kernel_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2505_00136_amd", "csrc", "gemm.hip")
 # timing kinds of the library's event hook -> kernel symbol, operand dtype.  The symbols are
 # the operand-mode specialisations that run for this workload's whole 2048-wide tiles
-# (update: KC/KC = 0, inversion: KC/MC = 1, trace: MC/MC = 3).
+# (update and trace: MC/MC = 3; the inversion's row-scaling launches are KC/MC = 1 and its
+# elimination launches MC/MC = 3, and the hook times both, hence `*`).
 TIMED_KERNELS = {
-    "fp64": ("gemm_update_kernel<double, 0>", "f64"), "fp32": ("gemm_update_kernel<float, 0>", "f32"),
-    "fp64_trtri": ("gemm_trtri_kernel<double, 1>", "f64"), "fp32_trtri": ("gemm_trtri_kernel<float, 1>", "f32"),
+    "fp64": ("gemm_update_kernel<double, 3>", "f64"), "fp32": ("gemm_update_kernel<float, 3>", "f32"),
+    "fp64_trtri": ("gemm_trtri_kernel<double, *>", "f64"), "fp32_trtri": ("gemm_trtri_kernel<float, *>", "f32"),
     "fp64_trace": ("gemm_trace_kernel<double, 3>", "f64"), "fp32_trace": ("gemm_trace_kernel<float, 3>", "f32"),
     "bf16x3": ("gemm_bf16x_kernel<3>", "bf16"), "bf16x6": ("gemm_bf16x_kernel<6>", "bf16"),
 }

@@ -217,6 +217,7 @@ struct CholWs {
   void* panel;      // copy of the panel below the diagonal tile (TRSM source)
   float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
   uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2, two sets
+  void* panel_t;    // transposed tiles of the solved panel (other modes), (T-1) b^2 elements, two sets
 
   void* arena;
   size_t arena_cap;
@@ -284,6 +285,25 @@ double add_trsm_job(Program& P, const TileLayout& L, void* K, int prec, const Ch
   return (double)(T - k - 1) * bd * bd * (bd + 1.0);
 }
 
+// Transposed copies of the solved panel k's tiles (float64 and float32 modes), buffer set
+// k mod 2: the trailing update reads both of its operands m-contiguous, the operand order
+// its main loop stages fastest (measured 4-5% over k-contiguous operands).
+void* panel_t_set(const TileLayout& L, const CholWs& w, int64_t k) {
+  return (char*)w.panel_t + (size_t)(k & 1) * (L.T - 1) * L.b * L.b * L.esize;
+}
+
+void describe_transpose(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
+  const int64_t b = L.b, T = L.T;
+  if (is_bf16(prec) || k >= T - 1) return;
+  const void* panel = L.off(K, k + 1, k);
+  void* dst = panel_t_set(L, w, k);
+  const int64_t count = T - k - 1;
+  const int es = L.esize;
+  const size_t bytes = (size_t)count * b * b * es;
+  P.kernel([=](hipStream_t s) { return launch_transpose_tiles(panel, dst, b, count, es, s); }, {span(panel, bytes)},
+           {span(dst, bytes)});
+}
+
 // hi/mid(/lo) bfloat16 planes of the solved panel k (split modes), buffer set k mod 2.
 void describe_split(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
   const int64_t b = L.b, T = L.T;
@@ -310,9 +330,11 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
   const bool mixed = is_mixed(prec), split = is_bf16(prec);
   const int64_t pstride = (T - 1) * b * b;
   const uint16_t* pl = split ? w.planes + (k & 1) * 3 * pstride : nullptr;
+  const char* pt = split ? nullptr : (const char*)panel_t_set(L, w, k);
   auto opnd = [&](int64_t m) -> const void* {
-    return split ? (const void*)(pl + (m - k - 1) * b * b) : (const void*)L.off(K, m, k);
+    return split ? (const void*)(pl + (m - k - 1) * b * b) : (const void*)(pt + (size_t)(m - k - 1) * b * b * L.esize);
   };
+  const int mode = split ? MODE_KC : MODE_MC;   // transposed panel tiles: element (r, c) at [c b + r]
   const double bd = (double)b;
   double syrk_flops = 0.0, gemm_flops = 0.0;
   for (int64_t nn = n0; nn < n1; ++nn) {
@@ -340,7 +362,7 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
         void* Cmn = L.off(K, m, nn);
         P.job(Cmn, b, Cmn, b, b, b, -1.0, 1.0, mixed ? JOB_C_F32 : 0);
       }
-      P.seg(opnd(m), b, MODE_KC, opnd(nn), b, MODE_KC, b, 0);
+      P.seg(opnd(m), b, mode, opnd(nn), b, mode, b, 0);
       if (split) P.segs.back().pstrideA = P.segs.back().pstrideB = pstride;
     }
   }
@@ -389,6 +411,7 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
       add_trsm_job(P, L, K, prec, w, k);
       P.gemm_end();
     }
+    describe_transpose(P, L, K, prec, w, k);
     describe_split(P, L, K, prec, w, k);
   };
   auto e1 = [](int64_t k) { return 1 + 2 * (int)k; };
@@ -440,6 +463,7 @@ CholSizes chol_sizes(const TileLayout& L, int prec) {
   c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   if (is_mixed(prec)) c.take<float>((size_t)L.b * L.b);
   if (is_bf16(prec)) c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b);
+  else c.take<char>((size_t)2 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   Program P1, P2;
   CholWs w{};
   describe_cholesky(P1, L, nullptr, prec, w, false);
@@ -454,6 +478,7 @@ CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
   w.panel = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.b * L.b) : nullptr;
   w.planes = is_bf16(prec) ? c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b) : nullptr;
+  w.panel_t = is_bf16(prec) ? nullptr : c.take<char>((size_t)2 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   w.arena = c.take<char>(0);
   w.arena_cap = ws_bytes > c.off ? ws_bytes - c.off : 0;
   return w;
@@ -590,7 +615,7 @@ VarWs carve_var(Carve& c, const TileLayout& L, int64_t m, int prec) {
 
 // ================================================================ gradient
 struct GradWs {
-  void* panel;      // copy of one block column of L: (T-1) b x b tiles
+  void* panel;      // block column of L with each tile transposed: (T-1) b x b tiles
   void* row;        // copy of one block row of the residual: (T-1) b x b tiles
   float* w32;       // T b x b (mixed)
   double* partial;  // [trace workgroups][3]
@@ -611,7 +636,7 @@ int64_t trace_workgroups(const TileLayout& L) {
 //   finalises block row j:     X_jc = L_jj^{-1} R_jc                  (c < j)
 //   eliminates block column j: R_ic -= L_ij X_jc (c < j), R_ij = -L_ij L_jj^{-1}  (i > j)
 // Each step is one launch of single-segment tile products sharing block row j and the
-// copied block column j, so concurrently running workgroups reuse the same operands.
+// transposed copy of block column j, so concurrently running workgroups reuse the same operands.
 void describe_trtri(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
   const int64_t b = L.b, T = L.T;
   const bool mixed = is_mixed(prec);
@@ -636,19 +661,22 @@ void describe_trtri(Program& P, const TileLayout& L, void* K, int prec, const Gr
       P.gemm_end();
     }
     if (j == T - 1) break;
+    // block column j of L, transposed tile by tile: both operands of the elimination are
+    // then m-contiguous, the operand order the main loop stages fastest
     const void* col = L.off(K, j + 1, j);
-    const size_t cbytes = (size_t)(T - j - 1) * tb;
-    P.kernel([=](hipStream_t s) { return launch_copy(w.panel, col, cbytes, s); });
+    const int64_t ncol = T - j - 1;
+    const int es = mixed ? 4 : 8;
+    P.kernel([=](hipStream_t s) { return launch_transpose_tiles(col, w.panel, b, ncol, es, s); });
     P.gemm_begin(mixed, GEMM_KIND_TRTRI, (double)(T - j - 1) * ((double)j * gemm + trmm));
     for (int64_t i = j + 1; i < T; ++i) {
       const void* Pi = (const char*)w.panel + (i - j - 1) * tb;
       for (int64_t c = 0; c < j; ++c) {
         void* C = L.off(K, i, c);
         P.job(C, b, C, b, b, b, -1.0, 1.0, cflag);
-        P.seg(Pi, b, MODE_KC, L.off(K, j, c), b, MODE_MC, b, 0);
+        P.seg(Pi, b, MODE_MC, L.off(K, j, c), b, MODE_MC, b, 0);
       }
       P.job(L.off(K, i, j), b, nullptr, 0, b, b, -1.0, 0.0, cflag);
-      P.seg(Pi, b, MODE_KC, Wd(j), b, MODE_MC, b, B_UPPER);
+      P.seg(Pi, b, MODE_MC, Wd(j), b, MODE_MC, b, B_UPPER);
     }
     P.gemm_end();
   }

@@ -546,18 +546,20 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
     else GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_GUARDED>));
   } else if (kind == GEMM_KIND_TRTRI) {
     if (prec_f32) {
-      if (spec == SPEC_KM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<float, SPEC_KM>));
+      if (spec == SPEC_MM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<float, SPEC_MM>));
+      else if (spec == SPEC_KM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<float, SPEC_KM>));
       else GPR_GRAD_LAUNCH((gemm_trtri_kernel<float, SPEC_GUARDED>));
     } else {
-      if (spec == SPEC_KM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<double, SPEC_KM>));
+      if (spec == SPEC_MM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<double, SPEC_MM>));
+      else if (spec == SPEC_KM) GPR_GRAD_LAUNCH((gemm_trtri_kernel<double, SPEC_KM>));
       else GPR_GRAD_LAUNCH((gemm_trtri_kernel<double, SPEC_GUARDED>));
     }
   } else if (kind == GEMM_KIND_UPDATE) {
     if (prec_f32) {
-      if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_update_kernel<float, SPEC_KK>));
+      if (spec == SPEC_MM) GPR_GEMM_LAUNCH((gemm_update_kernel<float, SPEC_MM>));
       else GPR_GEMM_LAUNCH((gemm_update_kernel<float, SPEC_GUARDED>));
     } else {
-      if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_update_kernel<double, SPEC_KK>));
+      if (spec == SPEC_MM) GPR_GEMM_LAUNCH((gemm_update_kernel<double, SPEC_MM>));
       else GPR_GEMM_LAUNCH((gemm_update_kernel<double, SPEC_GUARDED>));
     }
   } else {

@@ -39,6 +39,8 @@ hipError_t launch_convert_f64_f32(const double* src, float* dst, int64_t count, 
 // device copy with a kernel on `st` (16-byte vectors when aligned)
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t st);
+// dst tile t = transpose of src tile t, t < count, b x b row-major tiles of esize (4 or 8) bytes
+hipError_t launch_transpose_tiles(const void* src, void* dst, int64_t b, int64_t count, int esize, hipStream_t st);
 // zero `bytes` bytes at p (4-byte aligned pointer and size) with a kernel
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 

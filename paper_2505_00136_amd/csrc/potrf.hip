@@ -34,6 +34,32 @@ __global__ void copy16_kernel(const uint4* __restrict__ src, uint4* __restrict__
     dst[i] = src[i];
 }
 
+// dst tile t = (src tile t)^T for `count` consecutive b x b row-major tiles: one
+// 64 x 64 block per workgroup, read row-wise into LDS (one padding column against bank
+// conflicts) and written row-wise from its transpose, so both global sides are coalesced.
+template <typename E>
+__global__ __launch_bounds__(256)
+void transpose_tiles_kernel(const E* __restrict__ src, E* __restrict__ dst, int64_t b, int64_t nbt) {
+  __shared__ E blk[64][65];
+  const int64_t per_tile = nbt * nbt;
+  const int64_t t = blockIdx.x / per_tile, rem = blockIdx.x % per_tile;
+  const int64_t r0 = (rem / nbt) * 64, c0 = (rem % nbt) * 64;
+  const E* S = src + t * b * b;
+  E* D = dst + t * b * b;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t r = r0 + ty + 4 * q, c = c0 + tx;
+    if (r < b && c < b) blk[ty + 4 * q][tx] = S[r * b + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t r = c0 + ty + 4 * q, c = r0 + tx;   // D[r][c] = S[c][r]
+    if (r < b && c < b) D[r * b + c] = blk[tx][ty + 4 * q];
+  }
+}
+
 static int grid_for(int64_t count) {
   int64_t g = (count + 255) / 256;
   if (g > 65536) g = 65536;
@@ -99,6 +125,19 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_tiles(const void* src, void* dst, int64_t b, int64_t count, int esize, hipStream_t st) {
+  if (b <= 0 || count <= 0) return hipSuccess;
+  const int64_t nbt = (b + 63) / 64, blocks = count * nbt * nbt;
+  if (blocks > 0x7fffffff || (esize != 4 && esize != 8)) return hipErrorInvalidValue;
+  if (esize == 8)
+    hipLaunchKernelGGL(transpose_tiles_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, (const double*)src,
+                       (double*)dst, b, nbt);
+  else
+    hipLaunchKernelGGL(transpose_tiles_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, (const float*)src,
+                       (float*)dst, b, nbt);
   return hipGetLastError();
 }
 
