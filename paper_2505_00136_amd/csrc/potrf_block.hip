@@ -5,17 +5,18 @@
 // orchestration issues the block steps in stream order); this kernel handles the
 // diagonal block of each block step.  The block and its inverse live in registers:
 // 4 threads per row, thread t owns row t/4 and every fourth column starting at t%4, of
-// both L and W = L^{-1}.  One loop over the columns j does, with two barriers:
-//   pivot  L_jj = sqrt(A_jj), column j of L scaled by 1/L_jj, row j of W scaled by 1/L_jj,
-//   then   A_ik -= L_ij L_kj  (j < k <= i)  and  W_ic -= L_ij W_jc  (c <= j < i),
-// i.e. the right-looking Cholesky fused with forward elimination of L W = I.
-// Column j of L and row j of W are exchanged through two LDS vectors that are zero
-// outside their ranges (L_kj for k > j, W_jc for c <= j), so the rank-1 updates run
-// unmasked over all of a thread's columns: the entries they leave wrong (k > i) are
-// never stored.  The next pivot column is handed over in LDS by the threads that update
-// it, and column k of L keeps its unscaled value in registers until the final store
-// applies 1/L_kk, so no register is indexed at run time and no global store is pending
-// at any barrier.
+// both A (becoming L) and W = L^{-1}.  Column j is eliminated with unscaled operands:
+// with a = column j of A and w = row j of W as they stand after step j-1,
+// l_ij l_kj = a_ij a_kj / a_jj and l_ij W_jc = a_ij w_c / a_jj, so each row i > j updates
+//   A_ik -= c a_kj  and  W_ic -= c w_c,   c = a_ij (1/L_jj)^2,
+// the right-looking Cholesky fused with forward elimination of L W = I.  Column k of A
+// and row i of W keep their unscaled values in registers until the final store applies
+// 1/L_kk and 1/L_ii.  One barrier per column: the threads that update column j+1 during
+// step j publish it (and the row of W that step j finishes, and the next pivot) into the
+// other half of double-buffered LDS exchange vectors, which are zero outside their ranges
+// (a_kj for k > j, w_c for c <= j), so the updates run unmasked over all of a thread's
+// columns (the entries they leave wrong, k > i, are never stored) and no register is
+// indexed at run time.
 #include "common.h"
 #include "kernels.h"
 
@@ -27,12 +28,11 @@ __global__ __launch_bounds__(PB * 4)
 void potrf_block_kernel(double* __restrict__ A, int64_t lda, double* __restrict__ W, int64_t ldw, int jb,
                         int64_t col_base, unsigned long long* info) {
   constexpr int PQ = PB / 4;
-  // exchange vectors of step j, element k stored at [k % 4][k / 4] so that each thread's
-  // operands are contiguous: exl = column j of L (zero for k <= j), exw = row j of W
-  // (zero for c > j)
-  __shared__ __align__(16) double exl[4][PQ];
-  __shared__ __align__(16) double exw[4][PQ];
-  __shared__ double nextc[PB];    // current column j of A, before scaling
+  // exchange vectors of step j in buffer j % 2, element k stored at [k % 4][k / 4] so
+  // that each thread's operands are contiguous: exl = column j of A (zero for k <= j),
+  // exw = row j of W (zero for c > j)
+  __shared__ __align__(16) double exl[2][4][PQ];
+  __shared__ __align__(16) double exw[2][4][PQ];
   __shared__ double piv[PB];
   __shared__ double ipiv[PB];
   const int tid = threadIdx.x;
@@ -44,63 +44,68 @@ void potrf_block_kernel(double* __restrict__ A, int64_t lda, double* __restrict_
     ra[q] = (i < jb && k <= i) ? A[(int64_t)i * lda + k] : 0.0;
     rw[q] = (i < jb && k == i) ? 1.0 : 0.0;
   }
-  if (i < PQ) {
-    exl[cq][i] = 0.0;
-    exw[cq][i] = 0.0;
+  // step 0's operands: column 0 of A below the diagonal, row 0 of W, the first pivot
+  if (cq == 0) exl[0][i & 3][i >> 2] = (i > 0 && i < jb) ? ra[0] : 0.0;
+  if (i == 0) {
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) exw[0][cq][q] = rw[q];
+    if (cq == 0) {
+      const double d = ra[0];
+      if (!(d > 0.0)) atomicMin(info, (unsigned long long)(col_base + 1));
+      const double p = sqrt(d);
+      piv[0] = p;
+      ipiv[0] = 1.0 / p;
+    }
   }
-  if (cq == 0 && i < jb) nextc[i] = ra[0];
   __syncthreads();
   for (int j = 0; j < jb; ++j) {
-    if (i == j && cq == (j & 3)) {
-      const double d = nextc[j];
-      if (!(d > 0.0)) atomicMin(info, (unsigned long long)(col_base + j + 1));
-      const double p = sqrt(d);
-      piv[j] = p;
-      ipiv[j] = 1.0 / p;
-    }
-    __syncthreads();
-    const double inv = ipiv[j];
-    // column j of L (its own entry k = j leaves the update vector: zero)
-    if (cq == 0 && i >= j && i < jb) exl[i & 3][i >> 2] = i == j ? 0.0 : nextc[i] * inv;
-    if (i == j) {                                         // row j of W is final (zero beyond j)
-#pragma unroll
-      for (int q = 0; q < PQ; ++q) {
-        rw[q] *= inv;
-        exw[cq][q] = rw[q];
-      }
-    }
-    __syncthreads();
+    const int cur = j & 1, nxt = cur ^ 1, j1 = j + 1;
+    const bool owner = cq == (j1 & 3);   // this thread holds column j+1 of its row
     if (i > j && i < jb) {
-      const double li = exl[i & 3][i >> 2];
+      const double inv = ipiv[j];
+      const double c = exl[cur][i & 3][i >> 2] * (inv * inv);
       double el[PQ], ew[PQ];
 #pragma unroll
       for (int q = 0; q < PQ; q += 2) {
-        const double2 vl = *reinterpret_cast<const double2*>(&exl[cq][q]);
-        const double2 vw = *reinterpret_cast<const double2*>(&exw[cq][q]);
+        const double2 vl = *reinterpret_cast<const double2*>(&exl[cur][cq][q]);
+        const double2 vw = *reinterpret_cast<const double2*>(&exw[cur][cq][q]);
         el[q] = vl.x;
         el[q + 1] = vl.y;
         ew[q] = vw.x;
         ew[q + 1] = vw.y;
       }
-      const int j1 = j + 1;
       double nv = 0.0;
 #pragma unroll
       for (int q = 0; q < PQ; ++q) {
-        ra[q] = fma(-li, el[q], ra[q]);
-        rw[q] = fma(-li, ew[q], rw[q]);
+        ra[q] = fma(-c, el[q], ra[q]);
+        rw[q] = fma(-c, ew[q], rw[q]);
         nv = (cq + 4 * q == j1) ? ra[q] : nv;
       }
-      if (cq == (j1 & 3)) nextc[i] = nv;
+      if (owner) {
+        exl[nxt][i & 3][i >> 2] = i > j1 ? nv : 0.0;
+        if (i == j1) {
+          if (!(nv > 0.0)) atomicMin(info, (unsigned long long)(col_base + j1 + 1));
+          const double p = sqrt(nv);
+          piv[j1] = p;
+          ipiv[j1] = 1.0 / p;
+        }
+      }
+      if (i == j1) {                                        // row j+1 of W is final (unscaled)
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) exw[nxt][cq][q] = rw[q];
+      }
+    } else if (owner) {
+      exl[nxt][i & 3][i >> 2] = 0.0;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // column k of L kept its unscaled value in the registers since step k
+  // column k of A and row i of W kept their unscaled values in the registers
 #pragma unroll
   for (int q = 0; q < PQ; ++q) {
     const int k = cq + 4 * q;
     if (i < jb && k < jb) {
       A[(int64_t)i * lda + k] = k < i ? ra[q] * ipiv[k] : (k == i ? piv[k] : 0.0);
-      W[(int64_t)i * ldw + k] = k <= i ? rw[q] : 0.0;
+      W[(int64_t)i * ldw + k] = k <= i ? rw[q] * ipiv[i] : 0.0;
     }
   }
 }
