@@ -566,6 +566,7 @@ int solve_impl(const TileLayout& L, const void* K, const double* Z, int64_t d, H
 struct VarWs {
   void* V;         // T b x m (float64, or float32 in mixed modes); rows n.. are zero
   void* tmp;       // b x m
+  void* rowt;      // block row i of L with each tile transposed: (T-1) b x b tiles
   float* w32;      // T b x b float32 copies of the diagonal-tile inverses (mixed)
   double* partial; // column sums of squares
   void* arena;
@@ -579,11 +580,18 @@ void describe_var(Program& P, const TileLayout& L, const void* Kc, int64_t m, in
   const int cflag = mixed ? JOB_C_F32 : 0;
   for (int64_t i = 0; i < T; ++i) {
     char* Vi = (char*)w.V + (size_t)i * b * m * es;
-    // tmp = B_i - sum_{j<i} L_ij V_j
+    // tmp = B_i - sum_{j<i} L_ij V_j, with the tiles L_ij transposed first so that both
+    // operands are m-contiguous
+    if (i > 0) {
+      const void* obase = L.off(K, 1, 0);   // region O
+      void* rowt = w.rowt;
+      const int64_t Tt = T, bi = b;
+      P.kernel([=](hipStream_t s) { return launch_transpose_block_row(obase, Tt, i, rowt, bi, es, s); });
+    }
     P.gemm_begin(mixed);
     P.job(w.tmp, m, Vi, m, b, m, -1.0, 1.0, cflag);
     for (int64_t j = 0; j < i; ++j)
-      P.seg(L.off(K, i, j), b, MODE_KC, (char*)w.V + (size_t)j * b * m * es, m, MODE_MC, b, 0);
+      P.seg((char*)w.rowt + (size_t)j * b * b * es, b, MODE_MC, (char*)w.V + (size_t)j * b * m * es, m, MODE_MC, b, 0);
     P.gemm_end();
     // V_i = W_ii tmp
     P.gemm_begin(mixed);
@@ -607,6 +615,7 @@ VarWs carve_var(Carve& c, const TileLayout& L, int64_t m, int prec) {
   const int es = is_mixed(prec) ? 4 : 8;
   w.V = c.take<char>((size_t)L.npad() * m * es);
   w.tmp = c.take<char>((size_t)L.b * m * es);
+  w.rowt = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * es);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.T * L.b * L.b) : nullptr;
   w.partial = c.take<double>((size_t)ceil_div(std::max<int64_t>(L.n, 1), kRowsPerChunk) * m);
   w.arena = c.take<char>(0);

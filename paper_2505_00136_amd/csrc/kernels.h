@@ -41,6 +41,9 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t st);
 // dst tile t = transpose of src tile t, t < count, b x b row-major tiles of esize (4 or 8) bytes
 hipError_t launch_transpose_tiles(const void* src, void* dst, int64_t b, int64_t count, int esize, hipStream_t st);
+// dst tile j = transpose of tile (row, j) of region O (T x T tiles at obase), j < row
+hipError_t launch_transpose_block_row(const void* obase, int64_t T, int64_t row, void* dst, int64_t b, int esize,
+                                      hipStream_t st);
 // zero `bytes` bytes at p (4-byte aligned pointer and size) with a kernel
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 

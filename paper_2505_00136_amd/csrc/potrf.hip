@@ -34,17 +34,21 @@ __global__ void copy16_kernel(const uint4* __restrict__ src, uint4* __restrict__
     dst[i] = src[i];
 }
 
-// dst tile t = (src tile t)^T for `count` consecutive b x b row-major tiles: one
-// 64 x 64 block per workgroup, read row-wise into LDS (one padding column against bank
-// conflicts) and written row-wise from its transpose, so both global sides are coalesced.
+// dst tile t = (source tile t)^T for `count` b x b row-major tiles: one 64 x 64 block per
+// workgroup, read row-wise into LDS (one padding column against bank conflicts) and
+// written row-wise from its transpose, so both global sides are coalesced.  Source tile
+// t is src + t b^2 (row < 0), or tile (row, t) of a region O of T x T tiles at src
+// (column-major packed, index t (T-1) - t (t-1)/2 + (row - t - 1)).
 template <typename E>
 __global__ __launch_bounds__(256)
-void transpose_tiles_kernel(const E* __restrict__ src, E* __restrict__ dst, int64_t b, int64_t nbt) {
+void transpose_tiles_kernel(const E* __restrict__ src, E* __restrict__ dst, int64_t b, int64_t nbt, int64_t T,
+                            int64_t row) {
   __shared__ E blk[64][65];
   const int64_t per_tile = nbt * nbt;
   const int64_t t = blockIdx.x / per_tile, rem = blockIdx.x % per_tile;
   const int64_t r0 = (rem / nbt) * 64, c0 = (rem % nbt) * 64;
-  const E* S = src + t * b * b;
+  const int64_t st = row < 0 ? t : t * (T - 1) - t * (t - 1) / 2 + (row - t - 1);
+  const E* S = src + st * b * b;
   E* D = dst + t * b * b;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
@@ -128,17 +132,28 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_transpose_tiles(const void* src, void* dst, int64_t b, int64_t count, int esize, hipStream_t st) {
+static hipError_t transpose_common(const void* src, void* dst, int64_t b, int64_t count, int esize, int64_t T,
+                                   int64_t row, hipStream_t st) {
   if (b <= 0 || count <= 0) return hipSuccess;
   const int64_t nbt = (b + 63) / 64, blocks = count * nbt * nbt;
   if (blocks > 0x7fffffff || (esize != 4 && esize != 8)) return hipErrorInvalidValue;
   if (esize == 8)
     hipLaunchKernelGGL(transpose_tiles_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, (const double*)src,
-                       (double*)dst, b, nbt);
+                       (double*)dst, b, nbt, T, row);
   else
     hipLaunchKernelGGL(transpose_tiles_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, (const float*)src,
-                       (float*)dst, b, nbt);
+                       (float*)dst, b, nbt, T, row);
   return hipGetLastError();
+}
+
+hipError_t launch_transpose_tiles(const void* src, void* dst, int64_t b, int64_t count, int esize, hipStream_t st) {
+  return transpose_common(src, dst, b, count, esize, 0, -1, st);
+}
+
+hipError_t launch_transpose_block_row(const void* obase, int64_t T, int64_t row, void* dst, int64_t b, int esize,
+                                      hipStream_t st) {
+  if (row < 1 || row >= T) return row == 0 ? hipSuccess : hipErrorInvalidValue;
+  return transpose_common(obase, dst, b, row, esize, T, row, st);
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
