@@ -381,8 +381,9 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // stream; events order the two (e1(k): U1 of step k done, e2(k): panel k solved).  The
 // two streams touch disjoint tiles: U2 reads block column k and writes columns >= k+2,
 // the look-ahead work reads and writes block column k+1, diagonal tile k+1 and its
-// inverse, the panel copy and (split modes) the bfloat16 planes of panel k+1, which are
-// double-buffered by step parity.  The panel is staged by a copy kernel: a runtime
+// inverse, the panel copy and the operands of the next update built from panel k+1 (its
+// transposed tiles, or in the split modes its bfloat16 planes), which are double-buffered
+// by step parity.  The panel is staged by a copy kernel: a runtime
 // device-to-device copy issued on the auxiliary stream read stale panel data produced by
 // U1 on the other stream (run-to-run differences of 1e-5 in the solve residual at
 // n = 65536), which the copy kernel does not.
