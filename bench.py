@@ -110,7 +110,7 @@ def cpu_baseline(wl, seconds_budget=30.0):
         threads = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [os.cpu_count()])
     except Exception:
         threads = os.cpu_count()
-    n_s = 6144   # about 15-20 s of host work (assembly and three factorisations) on 16 cores
+    n_s = 8192   # about 10-15 s of host work (assembly and three or more factorisations) on 16 cores
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=n_s, n_test=1, D=wl["D"], seed=wl["seed"]))
     h = oracle.Hyper(math.sqrt(wl["D"]), 1.0, 0.01)
     t0 = time.perf_counter()
