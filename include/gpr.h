@@ -16,7 +16,14 @@
  *  - Matrices are row-major and contiguous: Z is n x d (row i = z_i), Zs is m x d.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it
  *    and calls return without waiting, except where a host output is documented;
- *    those calls synchronise `stream` before returning.
+ *    those calls synchronise `stream` before returning.  Calls that launch tile
+ *    products (gpr_cholesky, gpr_predict_var, gpr_nlml_grad, gpr_optimize) copy their
+ *    job tables through a ring of 8 pinned host slots per device; a call waits only when
+ *    all 8 hold copies that the GPU has not reached yet.
+ *  - Resources: the library allocates no device memory; the caller passes every buffer.
+ *    Its own host-side resources (the staging ring, an auxiliary stream of default
+ *    priority and events, per device) are created by gpr_init, or by the first call that
+ *    needs them on a device gpr_init did not cover, and kept until the process ends.
  *  - `tile` is the tile edge b, any b >= 1: T = ceil(n / b) tiles per dimension (T = 1
  *    is the untiled, sequential case).  When b does not divide n the tiled matrix has
  *    T b rows, and rows and columns n..Tb-1 are an identity block with a zero border,
@@ -104,6 +111,20 @@ GPR_API int gpr_version(void);
 /* Message of the last failing call on this thread (static storage, never NULL). */
 GPR_API const char* gpr_last_error(void);
 
+/* Set-up of the current device, outside any hot loop: creates the auxiliary stream and
+ * the events of the factorisation's look-ahead and the pinned staging ring of the job
+ * tables, sized for every call on problems up to n training points, m test points and
+ * tile edge `tile` in precision `prec` (n = 0: the minimum sizes).  Later calls on larger
+ * problems grow these resources when they first need them.  Optional: every call creates
+ * what it lacks.  Host only; may be called again (it only grows the resources). */
+GPR_API int gpr_init(int64_t n, int64_t m, int64_t tile, int prec);
+
+/* Schedule of gpr_cholesky, process-wide: on != 0 (the default) factors diagonal tile
+ * k+1 and its panel on the auxiliary stream while step k's remaining update runs on the
+ * caller's stream; 0 issues every launch on the caller's stream.  Both give the same
+ * bits.  Host only; takes effect for factorisations issued afterwards. */
+GPR_API int gpr_set_lookahead(int on);
+
 /* Bytes of the tiled matrix of an n x n covariance with tile edge `tile` in precision `prec`
  * (layout above).  bytes: host out. */
 GPR_API int gpr_tiles_bytes(int64_t n, int64_t tile, int prec, size_t* bytes);
@@ -126,9 +147,9 @@ GPR_API int gpr_assemble(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, i
  * regions D and O hold L (zero strictly-upper parts in D) and region W holds the
  * inverses of the diagonal tiles of L.  Diagonal tile k+1 and its panel are factored
  * on a second stream while the rest of step k's update runs on `stream` (events order
- * the two, and the call returns with all work ordered on `stream`).  The environment
- * variable GPR_CHOLESKY_LOOKAHEAD=0 puts every launch on `stream` instead; both
- * schedules give the same bits.
+ * the two, and the call returns with all work ordered on `stream`).  After
+ * gpr_set_lookahead(0) every launch goes to `stream` instead; both schedules give the
+ * same bits.
  * info: host out, or NULL.  When non-NULL the call synchronises `stream` and stores
  * 0, or the 1-based global column of the first non-positive pivot (LAPACK
  * convention), in which case it returns GPR_ERR_NOT_SPD and the factor is unspecified.
@@ -264,8 +285,10 @@ GPR_API int gpr_timing_enable(int on);
  *   2/3  bf16x3/bf16x6 trailing update (GEMM tiles only, as kind 1);
  *   4/5  float64/float32 step of the triangular inversion of the gradient (b^2 (b+1) per
  *        triangular tile product, 2 b^3 per full one);
- *   6/7  float64/float32 K^{-1} product fused with the gradient reduction (as kind 4/5;
- *        b (b+1)(2b+1)/3 for the product of two triangular tiles).
+ *   6/7  float64/float32 K^{-1} product fused with the gradient reduction (as kind 4/5
+ *        for tile pairs off the diagonal; a diagonal tile pair is symmetric and computed
+ *        on and below its diagonal only: b^2 (b+1) from full tiles, b (b+1)(b+2)/3 from
+ *        two triangular tiles; all launches of one gradient add up to about n^3 / 3).
  * Resets that kind's record.  All three are host outputs. */
 GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops);
 
@@ -284,7 +307,8 @@ GPR_API int gpr_cholesky_census(int64_t T, int64_t* counts);
  * without access ranges, waits issued before their event was recorded.  omit_event >= 0
  * analyses the schedule as if every wait on that event were missing (event 0: start,
  * 1 + 2k: column k+1 of step k updated, 2 + 2k: panel k solved); -1 analyses it as issued.
- * Touches no device memory.  Errors: GPR_ERR_PREC, GPR_ERR_SHAPE, GPR_ERR_ARG. */
+ * Touches no device memory.  Errors: GPR_ERR_ARG (unknown precision tag or NULL report),
+ * GPR_ERR_SHAPE. */
 GPR_API int gpr_cholesky_schedule_check(int64_t n, int64_t tile, int prec, int64_t omit_event, int64_t* report);
 
 #ifdef __cplusplus

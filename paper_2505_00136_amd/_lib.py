@@ -36,6 +36,8 @@ _vp, _i64, _int, _dbl, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctyp
 _SIGS = {
     "gpr_version": ([], _int),
     "gpr_last_error": ([], ctypes.c_char_p),
+    "gpr_init": ([_i64, _i64, _i64, _int], _int),
+    "gpr_set_lookahead": ([_int], _int),
     "gpr_tiles_bytes": ([_i64, _i64, _int, ctypes.POINTER(_sz)], _int),
     "gpr_workspace_size": ([_i64, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)], _int),
     "gpr_assemble": ([_vp, _i64, _i64, GprHyper, _i64, _int, _vp, _vp], _int),
@@ -136,6 +138,14 @@ def _prec(p) -> int:
 # ---------------------------------------------------------------- entry points
 def gpr_version() -> int:
     return load().gpr_version()
+
+
+def gpr_init(n=0, m=0, tile=1, prec="fp64"):
+    _check(load().gpr_init(n, m, tile, _prec(prec)))
+
+
+def gpr_set_lookahead(on: bool):
+    _check(load().gpr_set_lookahead(int(on)))
 
 
 def gpr_tiles_bytes(n, tile, prec) -> int:

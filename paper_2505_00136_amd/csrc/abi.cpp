@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -95,42 +96,68 @@ struct Carve {
   }
 };
 
-// Pinned staging buffer for the job tables; the event guards its reuse.
-struct Stager {
-  std::mutex mu;
-  void* host = nullptr;
+// Per-device resources, created by gpr_init (or, for a device gpr_init did not cover, by
+// the first call that needs them) and kept for the life of the process:
+//  - the look-ahead's auxiliary stream (default priority, non-blocking) and its events;
+//  - a ring of pinned staging slots for the job-table uploads.  Each slot is guarded by
+//    the event recorded after its copy, so a call waits only when the ring wraps onto a
+//    slot whose copy the GPU has not reached yet (kStageSlots uploads in flight).  A slot
+//    smaller than a call's tables is re-allocated, which gpr_init avoids by sizing the
+//    slots for the largest problem up front.
+constexpr int kMaxDevices = 64;
+constexpr int kStageSlots = 8;
+constexpr size_t kMinSlotBytes = (size_t)1 << 20;
+
+struct StageSlot {
+  char* host = nullptr;
   size_t cap = 0;
   hipEvent_t ev = nullptr;
-  int dev = -1;
+  bool inflight = false;
 };
-Stager g_stage;
 
-// Copies `bytes` from host memory to `dst` on `st` through the pinned staging buffer.
-int upload_blob(const void* data, size_t bytes, void* dst, hipStream_t st) {
-  if (bytes == 0) return GPR_OK;
-  std::lock_guard<std::mutex> lk(g_stage.mu);
+struct DevRes {
+  std::mutex mu;        // staging ring, stream and event pool
+  std::mutex chol_mu;   // factorisations that use the auxiliary stream and its events
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> events;
+  StageSlot slot[kStageSlots];
+  int next = 0;
+};
+DevRes g_res[kMaxDevices];
+
+int current_res(DevRes** r) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  // the previous upload (on whichever device) must have read the buffer before it is reused
-  if (g_stage.ev) HIPCHK(hipEventSynchronize(g_stage.ev));
-  if (g_stage.ev && g_stage.dev != dev) {   // a new device gets its own event
-    HIPCHK(hipEventDestroy(g_stage.ev));
-    g_stage.ev = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return fail(GPR_ERR_HIP, "device %d out of range", dev);
+  *r = &g_res[dev];
+  return GPR_OK;
+}
+
+// Grows every staging slot to `bytes` (R->mu held); waits for a slot's copy before freeing it.
+int grow_slots(DevRes* R, size_t bytes) {
+  bytes = std::max(bytes, kMinSlotBytes);
+  for (StageSlot& s : R->slot) {
+    if (!s.ev) HIPCHK(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+    if (s.cap >= bytes) continue;
+    if (s.inflight) HIPCHK(hipEventSynchronize(s.ev));
+    s.inflight = false;
+    if (s.host) HIPCHK(hipHostFree(s.host));
+    s.host = nullptr;
+    s.cap = 0;
+    HIPCHK(hipHostMalloc((void**)&s.host, bytes, hipHostMallocDefault));
+    s.cap = bytes;
   }
-  if (bytes > g_stage.cap) {
-    if (g_stage.host) HIPCHK(hipHostFree(g_stage.host));
-    g_stage.host = nullptr;
-    const size_t cap = bytes * 2 < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes * 2;
-    HIPCHK(hipHostMalloc(&g_stage.host, cap, hipHostMallocDefault));
-    g_stage.cap = cap;
+  return GPR_OK;
+}
+
+// Auxiliary stream and at least `nevents` events of the current device (R->mu held).
+int ensure_aux(DevRes* R, int nevents) {
+  if (!R->aux) HIPCHK(hipStreamCreateWithFlags(&R->aux, hipStreamNonBlocking));
+  while ((int)R->events.size() < nevents) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    R->events.push_back(e);
   }
-  if (!g_stage.ev) {
-    HIPCHK(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
-    g_stage.dev = dev;
-  }
-  memcpy(g_stage.host, data, bytes);
-  HIPCHK(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, st));
-  HIPCHK(hipEventRecord(g_stage.ev, st));
   return GPR_OK;
 }
 
@@ -139,46 +166,40 @@ size_t jobs_part(size_t nj) { return (nj * sizeof(GemmJob) + 255) & ~(size_t)255
 size_t arena_bytes_of(const Program& P) { return jobs_part(P.jobs.size()) + P.segs.size() * sizeof(GemmSeg) + 1024; }
 
 // Uploads the job and segment tables of P into `arena` (jobs first, segments at a
-// 256-byte boundary); returns the device addresses.
+// 256-byte boundary) through the next staging slot; returns the device addresses.
 int upload_tables(const Program& P, void* arena, size_t cap, hipStream_t st, const GemmJob** dj, const GemmSeg** ds) {
   const size_t jp = jobs_part(P.jobs.size());
   const size_t bytes = jp + P.segs.size() * sizeof(GemmSeg);
   if (bytes + 1024 > cap) return fail(GPR_ERR_WORKSPACE, "job-table arena too small (%zu > %zu)", bytes + 1024, cap);
-  std::vector<char> blob(bytes, 0);
-  if (!P.jobs.empty()) memcpy(blob.data(), P.jobs.data(), P.jobs.size() * sizeof(GemmJob));
-  if (!P.segs.empty()) memcpy(blob.data() + jp, P.segs.data(), P.segs.size() * sizeof(GemmSeg));
   *dj = (const GemmJob*)arena;
   *ds = (const GemmSeg*)((char*)arena + jp);
-  return upload_blob(blob.data(), bytes, arena, st);
+  if (bytes == 0) return GPR_OK;
+  DevRes* R = nullptr;
+  int rc = current_res(&R);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(R->mu);
+  if (R->slot[R->next].cap < bytes && (rc = grow_slots(R, bytes * 2))) return rc;
+  StageSlot& s = R->slot[R->next];
+  R->next = (R->next + 1) % kStageSlots;
+  if (!s.ev) HIPCHK(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+  if (s.inflight) HIPCHK(hipEventSynchronize(s.ev));   // the ring wrapped onto a copy still queued
+  if (!P.jobs.empty()) memcpy(s.host, P.jobs.data(), P.jobs.size() * sizeof(GemmJob));
+  if (!P.segs.empty()) memcpy(s.host + jp, P.segs.data(), P.segs.size() * sizeof(GemmSeg));
+  HIPCHK(hipMemcpyAsync(arena, s.host, bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(s.ev, st));
+  s.inflight = true;
+  return GPR_OK;
 }
 
-// Auxiliary stream (default priority, non-blocking) and event pool of the look-ahead, per
-// device, created on first use and kept for the life of the process.
-struct AuxState {
-  std::mutex mu;
-  int dev = -1;
-  hipStream_t aux = nullptr;
-  std::vector<hipEvent_t> events;
-};
-AuxState g_aux;
-
+// Auxiliary stream and events of the look-ahead on the current device.
 int aux_resources(int nevents, hipStream_t* aux, std::vector<hipEvent_t>** evs) {
-  std::lock_guard<std::mutex> lk(g_aux.mu);
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  if (g_aux.dev != dev) {
-    g_aux.aux = nullptr;
-    g_aux.events.clear();
-    g_aux.dev = dev;
-  }
-  if (!g_aux.aux) HIPCHK(hipStreamCreateWithFlags(&g_aux.aux, hipStreamNonBlocking));
-  while ((int)g_aux.events.size() < nevents) {
-    hipEvent_t e;
-    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    g_aux.events.push_back(e);
-  }
-  *aux = g_aux.aux;
-  *evs = &g_aux.events;
+  DevRes* R = nullptr;
+  int rc = current_res(&R);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(R->mu);
+  if ((rc = ensure_aux(R, nevents))) return rc;
+  *aux = R->aux;
+  *evs = &R->events;
   return GPR_OK;
 }
 
@@ -395,12 +416,9 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // diagonal block; that update shares its launch with the trailing update P_j P_j^T.
 int chol_events_needed(int64_t T) { return 1 + 2 * (int)T; }
 
-// The look-ahead is on unless the environment variable GPR_CHOLESKY_LOOKAHEAD=0 puts
-// every launch on the caller's stream (the two schedules give the same bits).
-bool cholesky_lookahead() {
-  const char* v = getenv("GPR_CHOLESKY_LOOKAHEAD");
-  return !(v && v[0] == '0');
-}
+// The look-ahead is on unless gpr_set_lookahead(0) puts every launch on the caller's
+// stream (the two schedules give the same bits).
+std::atomic<int> g_lookahead{1};
 
 void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, bool lookahead) {
   const int64_t T = L.T;
@@ -603,9 +621,11 @@ void describe_var(Program& P, const TileLayout& L, const void* Kc, int64_t m, in
   }
 }
 
+// Sigma = K_{Zs,Zs} - V^T V: float64 products and accumulation in every precision (the
+// mixed modes store V in float32 and widen each product to float64).
 void describe_fullcov(Program& P, const TileLayout& L, int64_t m, int prec, const VarWs& w, double* out) {
   const bool mixed = is_mixed(prec);
-  P.gemm_begin(mixed);
+  P.gemm_begin(0, mixed ? GEMM_KIND_WIDEN : GEMM_KIND_GENERIC);
   P.job(out, m, out, m, m, m, -1.0, 1.0, 0);
   P.seg(w.V, m, MODE_MC, w.V, m, MODE_MC, L.npad(), 0);
   P.gemm_end();
@@ -696,18 +716,22 @@ void describe_trtri(Program& P, const TileLayout& L, void* K, int prec, const Gr
 // to every lower tile pair j <= i <= k, and the trace epilogue contracts that contribution
 // with the gradient weights at once, so no K^{-1} tile is stored; alpha alpha^T is
 // subtracted once per tile pair, in the step k = i.  One launch per k, all of whose jobs
-// share block row k.
+// share block row k.  Diagonal tile pairs (i = j) are symmetric: only their macro tiles on
+// and below the diagonal run (the epilogue doubles the strictly-lower entries), so the
+// flops of all launches add up to those of the LAUUM product, about n^3 / 3.
 void describe_lauum_trace(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
   const int64_t b = L.b, T = L.T;
   const bool mixed = is_mixed(prec);
   const double bd = (double)b;
-  const double full = 2.0 * bd * bd * bd, tri1 = bd * bd * (bd + 1.0), tri2 = bd * (bd + 1.0) * (2.0 * bd + 1.0) / 3.0;
+  // a full tile product, a lower half of a symmetric or a triangular-times-full one, the
+  // lower half of a product of two triangular tiles
+  const double full = 2.0 * bd * bd * bd, half = bd * bd * (bd + 1.0), tri3 = bd * (bd + 1.0) * (bd + 2.0) / 3.0;
   auto Wd = [&](int64_t i) -> const void* {
     return mixed ? (const void*)(w.w32 + (size_t)i * b * b) : (const void*)L.winv(K, i);
   };
   for (int64_t k = 0; k < T; ++k) {
     const double kd = (double)k;
-    P.gemm_begin(mixed, GEMM_KIND_TRACE, kd * (kd + 1.0) / 2.0 * full + kd * tri1 + tri2);
+    P.gemm_begin(mixed, GEMM_KIND_TRACE, kd * (kd - 1.0) / 2.0 * full + 2.0 * kd * half + tri3);
     for (int64_t i = 0; i <= k; ++i) {
       const void* A = (i == k) ? Wd(k) : L.off(K, k, i);
       for (int64_t j = 0; j <= i; ++j) {
@@ -715,7 +739,8 @@ void describe_lauum_trace(Program& P, const TileLayout& L, void* K, int prec, co
         int tri = 0;
         if (i == k) tri |= A_UPPER;
         if (j == k) tri |= B_UPPER;
-        P.job(nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, i == k ? JOB_TRACE_ALPHA : 0, (int)i, (int)j);
+        const int flags = (i == k ? JOB_TRACE_ALPHA : 0) | (i == j ? JOB_LOWER_ONLY : 0);
+        P.job(nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, flags, (int)i, (int)j);
         P.seg(A, b, MODE_MC, Bp, b, MODE_MC, b, tri);
       }
     }
@@ -806,6 +831,28 @@ size_t optimize_state_bytes(int64_t n, int steps) {
   return c.off + 256;
 }
 
+// Largest job-table upload of any call on a problem of this size (staging slot size).
+size_t table_bytes(const TileLayout& L, int64_t m, int prec) {
+  size_t t = chol_sizes(L, prec).arena;
+  {
+    Carve c(nullptr);
+    VarWs w = carve_var(c, L, m, prec);
+    Program P;
+    describe_var(P, L, nullptr, m, prec, w);
+    describe_fullcov(P, L, m, prec, w, nullptr);
+    t = std::max(t, arena_bytes_of(P));
+  }
+  {
+    Carve c(nullptr);
+    GradWs w = carve_grad(c, L, prec);
+    Program P1, P2;
+    describe_trtri(P1, L, nullptr, prec, w);
+    describe_lauum_trace(P2, L, nullptr, prec, w);
+    t = std::max(t, std::max(arena_bytes_of(P1), arena_bytes_of(P2)));
+  }
+  return t;
+}
+
 size_t chol_ws_bytes(const TileLayout& L, int prec) {
   CholSizes s = chol_sizes(L, prec);
   return s.fixed + 256 + s.arena;
@@ -816,13 +863,15 @@ int chol_impl(void* K, const TileLayout& L, int prec, void* ws, size_t ws_bytes,
   CholWs w = carve_chol(ws, L, prec, ws_bytes);
   if (info_out) *info_out = w.info + 2;   // set by the factorisation's last kernel
 
-  const bool la = cholesky_lookahead();
+  const bool la = g_lookahead.load(std::memory_order_relaxed) != 0;
   if (!la)
     return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w, false); }, w.arena, w.arena_cap, st);
-  // the auxiliary stream and events are shared by all calls of this process: serialise
+  // the auxiliary stream and events are shared by all calls on this device: serialise
   // factorisations so that one call's events are not re-recorded by another
-  static std::mutex chol_mu;
-  std::lock_guard<std::mutex> lk(chol_mu);
+  DevRes* R = nullptr;
+  int rc = current_res(&R);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(R->chol_mu);
   return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w, true); }, w.arena, w.arena_cap, st,
                      nullptr, chol_events_needed(L.T));
 }
@@ -835,6 +884,30 @@ extern "C" {
 GPR_API int gpr_version(void) { return (1 << 16) | (0 << 8) | 0; }
 
 GPR_API const char* gpr_last_error(void) { return g_err; }
+
+GPR_API int gpr_init(int64_t n, int64_t m, int64_t tile, int prec) {
+  int rc;
+  if ((rc = check_prec(prec))) return rc;
+  if (n < 0 || m < 0) return fail(GPR_ERR_SHAPE, "need n, m >= 0");
+  if (n > 0 && (rc = check_shape(n, tile))) return rc;
+  size_t tb = kMinSlotBytes;
+  int nev = chol_events_needed(1);
+  if (n > 0) {
+    const TileLayout L = layout_of(n, tile, prec);
+    tb = std::max(tb, table_bytes(L, m, prec));
+    nev = chol_events_needed(L.T);
+  }
+  DevRes* R = nullptr;
+  if ((rc = current_res(&R))) return rc;
+  std::lock_guard<std::mutex> lk(R->mu);
+  if ((rc = ensure_aux(R, nev))) return rc;
+  return grow_slots(R, tb);
+}
+
+GPR_API int gpr_set_lookahead(int on) {
+  g_lookahead.store(on != 0 ? 1 : 0, std::memory_order_relaxed);
+  return GPR_OK;
+}
 
 GPR_API int gpr_tiles_bytes(int64_t n, int64_t tile, int prec, size_t* bytes) {
   int rc;

@@ -390,7 +390,8 @@ void gemm_tiles_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 }
 
 // float32-stored operands multiplied in float64 (exact products): the diagonal-tile
-// SYRK of the mixed-precision factorisations.
+// SYRK of the mixed-precision factorisations (KC/KC) and the full posterior covariance
+// V^T V of the mixed modes (MC/MC).
 template <int SPEC>
 __global__ __launch_bounds__(Shape<WN_FACTOR>::THREADS, 2)
 void gemm_widen_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
@@ -420,8 +421,9 @@ void gemm_trtri_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
 // log l (nu exp(-u) 2u = K_f r^2 / l^2; the Matern forms from u), u = r^2 / (2 l^2) read
 // from the tile pair's precomputed half scaled squared distances, and the workgroup
 // writes its three partial sums
-// (sum w k 2u, sum w k, sum over the diagonal of w; off-diagonal tile pairs count twice)
-// to partial[blockIdx.x][0..2].
+// (sum w k 2u, sum w k, sum over the diagonal of w; off-diagonal tile pairs count twice,
+// and a diagonal tile pair, computed on and below its diagonal only (JOB_LOWER_ONLY),
+// counts its strictly-lower entries twice) to partial[blockIdx.x][0..2].
 template <typename T, int SPEC>
 __global__ __launch_bounds__(Shape<WN_GRAD>::THREADS, 2)
 void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs,
@@ -450,7 +452,7 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
     double ell, nu, s2;
     resolve_hyper(ta.h, ell, nu, s2);
     const int64_t ti = job.aux0, tj = job.aux1;
-    const double wt = (ti == tj) ? 1.0 : 2.0;
+    const bool diag_tile = ti == tj;
     const bool with_alpha = job.flags & JOB_TRACE_ALPHA;
     const double* __restrict__ U = ta.u + (ti * (ti + 1) / 2 + tj) * ta.b * ta.b;
 #pragma unroll
@@ -461,7 +463,10 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
         for (int r = 0; r < 4; ++r) {
           const int row = m0 + wm + i * 16 + Op::row(lane, r);
           const int col = n0 + wn + j * 16 + (lane & 15);
-          if (row < job.M && col < job.N) {
+          // a diagonal tile pair is symmetric and computed on and below its diagonal
+          // only: the strictly-lower entries count twice, the upper ones not at all
+          const double wt = !diag_tile || row > col ? 2.0 : (row == col ? 1.0 : 0.0);
+          if (row < job.M && col < job.N && wt != 0.0) {
             const double u = U[(int64_t)row * ta.b + col];
             double w = (double)acc[i][j][r];
             if (with_alpha) w -= ta.alpha[ti * ta.b + row] * ta.alpha[tj * ta.b + col];
@@ -475,7 +480,7 @@ void gemm_trace_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restri
               s_l = fma(wt * w, dl, s_l);
               s_nu = fma(wt * w, kf, s_nu);
             }
-            if (ti == tj && row == col) s_s += w;
+            if (diag_tile && row == col) s_s += w;
           }
         }
   }
@@ -543,6 +548,7 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
   if (kind == GEMM_KIND_TRACE) return hipErrorInvalidValue;   // launched by launch_gemm_trace
   if (kind == GEMM_KIND_WIDEN) {
     if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_KK>));
+    else if (spec == SPEC_MM) GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_MM>));
     else GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_GUARDED>));
   } else if (kind == GEMM_KIND_TRTRI) {
     if (prec_f32) {

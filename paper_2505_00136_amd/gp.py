@@ -87,13 +87,14 @@ class GP:
         _lib.gpr_nlml(self._K, self.n, self.tile, self.prec, self.y, self.alpha, out)
         return out[0]
 
-    def grad(self) -> torch.Tensor:
-        """dNLML/dlog(l, nu, sigma^2); consumes the factor (the next call refactors)."""
+    def grad(self, trainable: Sequence[int] | None = None) -> torch.Tensor:
+        """dNLML/dlog(l, nu, sigma^2); consumes the factor (the next call refactors).
+        Entries whose `trainable` flag is 0 (default: the GP's flags) are returned as 0."""
         self._need_factor()
         ws, wsb = self._workspace()
         g = torch.empty(3, dtype=torch.float64, device=self.device)
         _lib.gpr_nlml_grad(self.Z, self.n, self.d, self._h, self._K, self.tile, self.prec, self.alpha,
-                           self.trainable, g, ws, wsb)
+                           self.trainable if trainable is None else tuple(trainable), g, ws, wsb)
         self._factored = False
         return g
 
@@ -140,24 +141,34 @@ class GP:
 class NLMLFunction(torch.autograd.Function):
     """NLML(theta_log) with the hand-written backward kernel behind it.
 
-    forward(theta_log[3], gp) -> device scalar; backward returns gout * dNLML/dtheta_log.
-    The GP object supplies data, tile configuration and precision; its
-    hyperparameters are set from theta_log.
+    forward(theta_log[3], gp) -> device scalar; backward returns gout * dNLML/dtheta_log,
+    all three entries (the GP's trainable flags do not mask it).  The GP object supplies
+    data, tile configuration and precision; forward sets its hyperparameters from
+    theta_log.  Each forward keeps its own theta: a backward whose GP has been refitted
+    at another theta since (another forward, a fit, an optimisation) or whose factor was
+    consumed refits at the saved theta first, so any number of forwards may precede the
+    backwards.
     """
 
     @staticmethod
     def forward(ctx, theta_log, gp: GP):
         vals = theta_log.detach().to("cpu", torch.float64).tolist()
-        gp.hyper = tuple(math.exp(v) for v in vals)
+        hyper = tuple(math.exp(v) for v in vals)
+        gp.hyper = hyper
         gp.fit()
         out = gp.nlml().clone().to(theta_log.device)
         ctx.gp = gp
+        ctx.hyper = hyper
         ctx.theta_device = theta_log.device
         return out
 
     @staticmethod
     def backward(ctx, gout):
-        g = ctx.gp.grad().to(ctx.theta_device)
+        gp = ctx.gp
+        if gp.hyper != ctx.hyper or not gp._factored:
+            gp.hyper = ctx.hyper
+            gp.fit()
+        g = gp.grad(trainable=(1, 1, 1)).to(ctx.theta_device)
         return gout * g, None
 
 

@@ -115,14 +115,17 @@ def test_factorisation_bitwise_reproducible(full):
     assert torch.equal(alpha2, full["alpha"]) and nlml2 == full["nlml"]
 
 
-def test_lookahead_matches_single_stream_bitwise(full, monkeypatch):
+def test_lookahead_matches_single_stream_bitwise(full):
     """The two-stream factorisation (look-ahead) and the one-stream schedule perform the
     same arithmetic per element, so they give the same bits; repeated look-ahead
     factorisations agree too.  (A read-modify-write of the LDS exchange vector in the
     diagonal-block kernel once raced with other waves and made the look-ahead differ.)"""
-    monkeypatch.setenv("GPR_CHOLESKY_LOOKAHEAD", "0")
-    a0, n0 = full["fit"](H)
-    monkeypatch.setenv("GPR_CHOLESKY_LOOKAHEAD", "1")
+    lib = full["lib"]
+    lib.gpr_set_lookahead(False)
+    try:
+        a0, n0 = full["fit"](H)
+    finally:
+        lib.gpr_set_lookahead(True)
     runs = [full["fit"](H) for _ in range(3)]
     for a1, n1 in runs:
         assert torch.equal(a1, a0) and n1 == n0

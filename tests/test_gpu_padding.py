@@ -129,14 +129,17 @@ def test_padded_optimize_matches_oracle_adam(lib):
     np.testing.assert_allclose(tr, tr_o, rtol=1e-10)
 
 
-def test_padded_lookahead_matches_single_stream(lib, monkeypatch):
+def test_padded_lookahead_matches_single_stream(lib):
     """The two factorisation schedules give the same bits on a padded matrix."""
     n, tile, D = 1000, 128, 5
     Z, y, _ = _data(n, D, 17)
     h = Hyper(1.0, 1.0, 0.02)
     g1 = _gpu_fit(lib, Z, y, h, tile)
-    monkeypatch.setenv("GPR_CHOLESKY_LOOKAHEAD", "0")
-    g0 = _gpu_fit(lib, Z, y, h, tile)
+    lib.gpr_set_lookahead(False)
+    try:
+        g0 = _gpu_fit(lib, Z, y, h, tile)
+    finally:
+        lib.gpr_set_lookahead(True)
     assert torch.equal(g1["K"], g0["K"]) and torch.equal(g1["alpha"], g0["alpha"])
 
 
