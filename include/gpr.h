@@ -161,8 +161,11 @@ GPR_API int gpr_cholesky(void* K_tiles, int64_t n, int64_t tile, int prec, void*
  * over the tiles (Section 4.2; alpha feeds Eq. 3 and Eq. 5).  With refine_sweeps > 0
  * each sweep computes the float64 residual r = y - K alpha with K regenerated from Z
  * and h (never stored), solves for the correction with the factor and adds it;
- * this lifts a mixed-precision factor to float64 accuracy.  Z and h are read only
- * when refine_sweeps > 0.  y: n (in), alpha: n (out; may not alias y). */
+ * this lifts a mixed-precision factor to float64 accuracy.  refine_sweeps < 0 takes the
+ * precision's default, which gpr_optimize uses too: 0 for GPR_FP64, 3 for GPR_FP32 and
+ * GPR_BF16X6, 6 for GPR_BF16X3 (each sweep contracts the error by about kappa u of the
+ * factor).  Z and h are read only when sweeps are run.  y: n (in), alpha: n (out; may
+ * not alias y). */
 GPR_API int gpr_solve(const void* L_tiles, const double* Z, int64_t n, int64_t d, gpr_hyper_t h, int64_t tile,
                       int prec, const double* y, double* alpha, int refine_sweeps, void* ws, size_t ws_bytes,
                       void* stream);

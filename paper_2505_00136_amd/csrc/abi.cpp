@@ -42,8 +42,16 @@ int fail(int code, const char* fmt, ...) {
 constexpr int64_t kInnerBlock = 64;     // block edge of the in-tile factorisation loop
 constexpr int64_t kRowsPerChunk = 256;  // rows per workgroup of the transposed matrix-vector products
 constexpr int64_t kColsPerChunk = 4096; // training points per workgroup of the fused kernel-vector products
+constexpr int GPR_BF16X3_SWEEPS = 6;    // default refinement sweeps of the three-product split
 
 bool is_mixed(int prec) { return prec != GPR_FP64; }
+// Refinement sweeps of gpr_solve (refine_sweeps < 0) and gpr_optimize per precision: none
+// in float64; with a factor of unit roundoff u each sweep contracts the error of alpha by
+// about kappa u, so the split-bfloat16 mode with three products (u ~ 2^-16) needs more
+// sweeps than float32 and bf16x6 (u ~ 2^-24) to reach the same accuracy.
+int default_sweeps(int prec) {
+  return prec == GPR_FP64 ? 0 : (prec == GPR_BF16X3 ? GPR_BF16X3_SWEEPS : 3);
+}
 bool is_bf16(int prec) { return prec == GPR_BF16X3 || prec == GPR_BF16X6; }
 int esize_of(int prec) { return is_mixed(prec) ? 4 : 8; }
 
@@ -984,7 +992,7 @@ GPR_API int gpr_solve(const void* L_tiles, const double* Z, int64_t n, int64_t d
   int rc;
   if ((rc = check_prec(prec))) return rc;
   if ((rc = check_shape(n, tile))) return rc;
-  if (refine_sweeps < 0) return fail(GPR_ERR_ARG, "refine_sweeps must be >= 0");
+  if (refine_sweeps < 0) refine_sweeps = default_sweeps(prec);
   if (n == 0) return GPR_OK;
   if (!L_tiles || !y || !alpha || !ws) return fail(GPR_ERR_ARG, "null pointer");
   if (y == alpha) return fail(GPR_ERR_ARG, "alpha may not alias y");
@@ -1154,7 +1162,7 @@ GPR_API int gpr_optimize(const double* Z, const double* y, int64_t n, int64_t d,
       Carve c2(ws2);
       c2.take<unsigned long long>(32);   // keep the factorisation's info word intact
       SolveWs sw = carve_solve(c2, L);
-      if ((rc = solve_impl(L, K_tiles, Z, d, hd, y, dalpha, is_mixed(prec) ? 3 : 0, sw, st))) return rc;
+      if ((rc = solve_impl(L, K_tiles, Z, d, hd, y, dalpha, default_sweeps(prec), sw, st))) return rc;
     }
     HIPCHK(launch_nlml(L.diag(K_tiles, 0), L.b, L.n, y, dalpha, dtrace + s, st));
     if (s == steps) break;

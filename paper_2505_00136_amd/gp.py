@@ -41,7 +41,8 @@ class GP:
         if kernel not in _lib.KERNELS:
             raise ValueError(f"kernel must be one of {sorted(_lib.KERNELS)}")
         self.kernel = kernel
-        self.refine_sweeps = refine_sweeps if refine_sweeps is not None else (0 if prec == "fp64" else 3)
+        # None: the library's default for the precision (none in float64)
+        self.refine_sweeps = -1 if refine_sweeps is None else int(refine_sweeps)
         self._K = torch.empty(_lib.gpr_tiles_bytes(self.n, self.tile, prec), dtype=torch.uint8, device=self.device)
         self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
         self.alpha = None

@@ -15,6 +15,8 @@ import datagen
 import oracle
 from oracle import Hyper
 
+from tests.checks import assert_close, assert_elementwise  # noqa: E402,F401
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +36,10 @@ def test_matern_fit_predict_gradient(lib, kernel, n, tile, D):
     L, a, f = oracle.fit(Z, y, h)
     g = _gpu_fit(lib, Z, y, h, tile, m=33)
     assert abs(g["nlml"] - f) / abs(f) < 1e-10
-    assert _rel(g["alpha"].cpu().numpy(), a) < 1e-10
+    assert_close(g["alpha"].cpu().numpy(), a, 1e-10)
     mean, var = _gpu_predict(lib, g, Zs, h)
-    assert _rel(mean, oracle.predict_mean(Z, Zs, h, a)) < 1e-10
-    assert _rel(var, oracle.predict_var(Z, Zs, h, L)) < 1e-10
+    assert_close(mean, oracle.predict_mean(Z, Zs, h, a), 1e-10)
+    assert_close(var, oracle.predict_var(Z, Zs, h, L), 1e-10)
     _, S = _gpu_predict(lib, g, Zs, h, full_cov=True)
     So = oracle.predict_var(Z, Zs, h, L, full_cov=True)
     assert np.max(np.abs(S - So)) < 1e-10 * max(1.0, np.max(np.abs(So)))
@@ -75,7 +77,7 @@ def test_matern_float32_path_with_refinement(lib):
     g = _gpu_fit(lib, Z, y, h, tile, prec="fp32", sweeps=3, m=64)
     assert abs(g["nlml"] - f) / abs(f) < 1e-6
     mean, var = _gpu_predict(lib, g, Zs, h)
-    assert _rel(mean, oracle.predict_mean(Z, Zs, h, a)) < 1e-6
+    assert_close(mean, oracle.predict_mean(Z, Zs, h, a), 1e-6)
     assert np.max(np.abs(var - oracle.predict_var(Z, Zs, h, L))) < 1e-4
 
 
@@ -88,4 +90,4 @@ def test_gp_front_end_with_a_matern_kernel(lib):
     L, a, f = oracle.fit(ds.Z, ds.y, h)
     assert float(gp.nlml().item()) == pytest.approx(f, rel=1e-10)
     mean = gp.predict(ds.Zs).cpu().numpy()
-    assert _rel(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a)) < 1e-10
+    assert_close(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a), 1e-10)

@@ -18,6 +18,8 @@ import datagen
 import oracle
 from oracle import Hyper
 
+from tests.checks import assert_close, assert_elementwise  # noqa: E402,F401
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +56,7 @@ def test_padded_factor_is_bordered_by_identity(lib, n, tile, D):
     np.testing.assert_array_equal(Wl[r:, r:], np.eye(tile - r))
     assert np.all(Wl[r:, :r] == 0.0)
     assert abs(g["nlml"] - f) / abs(f) < 1e-10
-    assert _rel(g["alpha"].cpu().numpy(), a) < 1e-10
+    assert_close(g["alpha"].cpu().numpy(), a, 1e-10)
 
 
 @pytest.mark.parametrize("n,tile,D", CASES)
@@ -65,8 +67,8 @@ def test_padded_posterior_and_gradient(lib, n, tile, D):
     m = Zs.shape[0]
     g = _gpu_fit(lib, Z, y, h, tile, m=m)
     mean, var = _gpu_predict(lib, g, Zs, h)
-    assert _rel(mean, oracle.predict_mean(Z, Zs, h, a)) < 1e-10
-    assert _rel(var, oracle.predict_var(Z, Zs, h, L)) < 1e-10
+    assert_close(mean, oracle.predict_mean(Z, Zs, h, a), 1e-10)
+    assert_close(var, oracle.predict_var(Z, Zs, h, L), 1e-10)
     _, S = _gpu_predict(lib, g, Zs, h, full_cov=True)
     So = oracle.predict_var(Z, Zs, h, L, full_cov=True)
     assert np.max(np.abs(S - So)) < 1e-10 * max(1.0, np.max(np.abs(So)))
@@ -85,7 +87,7 @@ def test_padded_matern_gradient(lib, kernel):
     g = _gpu_fit(lib, Z, y, h, tile, m=Zs.shape[0])
     assert abs(g["nlml"] - f) / abs(f) < 1e-10
     mean, var = _gpu_predict(lib, g, Zs, h)
-    assert _rel(var, oracle.predict_var(Z, Zs, h, L)) < 1e-10
+    assert_close(var, oracle.predict_var(Z, Zs, h, L), 1e-10)
     grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
     lib.gpr_nlml_grad(g["Z"], n, D, h, g["K"], tile, "fp64", g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
     go = oracle.nlml_grad(Z, h, L, a)
@@ -103,10 +105,10 @@ def test_padded_mixed_precision(lib, prec):
     assert np.max(np.abs(Lg[:1000, :1000] - L)) / np.max(np.abs(L)) < 1e-4
     assert np.all(Lg[1000:, :1000] == 0.0) and np.array_equal(Lg[1000:, 1000:], np.eye(152))
     assert abs(g["nlml"] - f) / abs(f) < 1e-6
-    assert _rel(g["alpha"].cpu().numpy(), a) < 1e-6
+    assert_close(g["alpha"].cpu().numpy(), a, 1e-6)
     mean, var = _gpu_predict(lib, g, ds.Zs, h)
-    assert _rel(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a)) < 1e-6
-    assert _rel(var, oracle.predict_var(ds.Z, ds.Zs, h, L)) < 1e-4
+    assert_close(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a), 1e-6)
+    assert_close(var, oracle.predict_var(ds.Z, ds.Zs, h, L), 1e-4)
     go = oracle.nlml_grad(ds.Z, h, L, a)
     grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
     lib.gpr_nlml_grad(g["Z"], 1000, 8, h, g["K"], tile, prec, g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
@@ -152,4 +154,4 @@ def test_gp_front_end_with_a_tile_that_does_not_divide_n(lib):
     L, a, f = oracle.fit(ds.Z, ds.y, h)
     assert float(gp.nlml().item()) == pytest.approx(f, rel=1e-10)
     mean = gp.predict(ds.Zs).cpu().numpy()
-    assert _rel(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a)) < 1e-10
+    assert_close(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a), 1e-10)

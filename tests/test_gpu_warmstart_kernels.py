@@ -7,6 +7,8 @@ import pytest
 import datagen
 import oracle
 
+from tests.checks import assert_elementwise  # noqa: E402
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -63,6 +65,9 @@ def test_mlp_forward_and_gradient_parity(lib):
     assert np.linalg.norm(g - go) / np.linalg.norm(go) < 1e-4
     for blk in (slice(0, 4096), slice(4096, 4224), slice(4224, 20608), slice(20608, 20736), slice(20736, 21123)):
         assert np.linalg.norm(g[blk] - go[blk]) / max(np.linalg.norm(go[blk]), 1e-30) < 1e-4
+        # per entry, within each layer's weights or biases: float32 accumulation over the
+        # batch and the layer width (~128 terms) against the float64 oracle
+        assert_elementwise(g[blk], go[blk], 1e-3, what=f"mlp gradient {blk}")
 
 
 def test_mlp_train_step_adam(lib):

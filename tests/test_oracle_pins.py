@@ -252,6 +252,35 @@ def test_optimize_trace_semantics():
     assert tr[-1] < tr[0]
 
 
+def test_optimize_trajectory_vs_torch_adam():
+    """oracle.optimize takes each gradient at the current theta: its trajectory equals
+    torch.optim.Adam on the log-hyperparameters driven by the oracle's gradient at the
+    parameters torch holds at each step (a gradient at a stale theta, or an update
+    applied before the NLML is recorded, would depart from it after the first step)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(16)
+    Z = rng.normal(size=(80, 3))
+    y = np.sin(Z[:, 0]) - 0.5 * Z[:, 2] + 0.1 * rng.normal(size=80)
+    theta0 = (0.3, -0.2, math.log(0.05))
+    steps, lr = 3, 0.2
+    theta, tr = oracle.optimize(Z, y, theta0, steps=steps, lr=lr)
+    p = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    want = []
+    for _ in range(steps):
+        h = Hyper.from_log(p.detach().numpy())
+        L, a, f = oracle.fit(Z, y, h)
+        want.append(f)
+        opt.zero_grad()
+        p.grad = torch.tensor(oracle.nlml_grad(Z, h, L, a), dtype=torch.float64)
+        opt.step()
+    want.append(oracle.fit(Z, y, Hyper.from_log(p.detach().numpy()))[2])
+    np.testing.assert_allclose(theta, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(tr, want, rtol=1e-13)
+    # the steps really move theta (so a stale gradient would be seen)
+    assert np.all(np.abs(theta - np.array(theta0)) > 0.1)
+
+
 # ---------------------------------------------------------------- P15, P16: variance bounds, interpolation
 def test_variance_bounds_and_interpolation():
     rng = np.random.default_rng(16)
