@@ -175,6 +175,17 @@ GPR_API int gpr_solve(const void* L_tiles, const double* Z, int64_t n, int64_t d
 GPR_API int gpr_predict(const double* Z, int64_t n, const double* Zs, int64_t m, int64_t d, gpr_hyper_t h,
                         const double* alpha, double* mean, void* ws, size_t ws_bytes, void* stream);
 
+/* gpr_predict without a workspace, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same result, bit for bit, with the partial sums in a fixed device array of the library
+ * (16 MiB per GPU, held until the process ends; its address is looked up by gpr_init or
+ * by the first call on a device).  The call allocates nothing.  Sizes: ceil(n / 4096) * m
+ * must not exceed 2^21 (e.g. m <= 131072 at n = 65536), else GPR_ERR_WORKSPACE.  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (different streams
+ * without ordering between them) race and must not be issued.  n = 0 writes zeros. */
+GPR_API int gpr_predict_noalloc(const double* Z, int64_t n, const double* Zs, int64_t m, int64_t d, gpr_hyper_t h,
+                                const double* alpha, double* mean, void* stream);
+
 /* Posterior uncertainty, Eq. 4, from the factor: V = L^{-1} K_{Z,Zs} by one tiled
  * forward substitution with m right-hand sides (the same substitution that serves
  * the mean; Section 5.1), then

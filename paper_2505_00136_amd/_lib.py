@@ -44,6 +44,7 @@ _SIGS = {
     "gpr_cholesky": ([_vp, _i64, _i64, _int, _vp, _sz, ctypes.POINTER(_i64), _vp], _int),
     "gpr_solve": ([_vp, _vp, _i64, _i64, GprHyper, _i64, _int, _vp, _vp, _int, _vp, _sz, _vp], _int),
     "gpr_predict": ([_vp, _i64, _vp, _i64, _i64, GprHyper, _vp, _vp, _vp, _sz, _vp], _int),
+    "gpr_predict_noalloc": ([_vp, _i64, _vp, _i64, _i64, GprHyper, _vp, _vp, _vp], _int),
     "gpr_predict_var": ([_vp, _i64, _vp, _i64, _i64, GprHyper, _vp, _i64, _int, _int, _int, _vp, _vp, _sz, _vp], _int),
     "gpr_nlml": ([_vp, _i64, _i64, _int, _vp, _vp, _vp, _vp], _int),
     "gpr_nlml_grad": ([_vp, _i64, _i64, GprHyper, _vp, _i64, _int, _vp, ctypes.POINTER(_int), _vp, _vp, _sz, _vp], _int),
@@ -183,6 +184,11 @@ def gpr_solve(L_tiles, Z, n, d, h, tile, prec, y, alpha, refine_sweeps, ws, ws_b
 def gpr_predict(Z, n, Zs, m, d, h, alpha, mean, ws, ws_bytes, stream=None):
     _check(load().gpr_predict(_ptr(Z), n, _ptr(Zs), m, d, hyper(h), _ptr(alpha), _ptr(mean), _ptr(ws), ws_bytes,
                               _stream(stream)))
+
+
+def gpr_predict_noalloc(Z, n, Zs, m, d, h, alpha, mean, stream=None):
+    _check(load().gpr_predict_noalloc(_ptr(Z), n, _ptr(Zs), m, d, hyper(h), _ptr(alpha), _ptr(mean),
+                                      _stream(stream)))
 
 
 def gpr_predict_var(Z, n, Zs, m, d, h, L_tiles, tile, prec, full_cov, add_noise, out, ws, ws_bytes, stream=None):

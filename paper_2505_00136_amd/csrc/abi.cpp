@@ -907,6 +907,7 @@ GPR_API int gpr_init(int64_t n, int64_t m, int64_t tile, int prec) {
   }
   DevRes* R = nullptr;
   if ((rc = current_res(&R))) return rc;
+  HIPCHK(scratch_setup(nullptr));   // address of this device's scratch for gpr_predict_noalloc
   std::lock_guard<std::mutex> lk(R->mu);
   if ((rc = ensure_aux(R, nev))) return rc;
   return grow_slots(R, tb);
@@ -1024,6 +1025,31 @@ GPR_API int gpr_predict(const double* Z, int64_t n, const double* Zs, int64_t m,
   double* partial = (double*)ws;
   HIPCHK(launch_kmatvec_partial(Zs, m, Z, n, d, harg(h), alpha, partial, kColsPerChunk, st));
   HIPCHK(launch_reduce_partials(partial, ceil_div(n, kColsPerChunk), m, 1.0, nullptr, 0.0, mean, st));
+  return GPR_OK;
+}
+
+GPR_API int gpr_predict_noalloc(const double* Z, int64_t n, const double* Zs, int64_t m, int64_t d, gpr_hyper_t h,
+                                const double* alpha, double* mean, void* stream) {
+  int rc;
+  if ((rc = check_hyper(h))) return rc;
+  if (n < 0 || m < 0 || d < 1) return fail(GPR_ERR_SHAPE, "need n, m >= 0 and d >= 1");
+  if (m == 0) return GPR_OK;
+  if (!Zs || !mean) return fail(GPR_ERR_ARG, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) {
+    HIPCHK(launch_fill_u64((unsigned long long*)mean, 0ull, m, st));   // +0.0 bits
+    return GPR_OK;
+  }
+  if (!Z || !alpha) return fail(GPR_ERR_ARG, "null pointer");
+  const int64_t nch = ceil_div(n, kColsPerChunk);
+  if (m > kScratchDoubles / nch)
+    return fail(GPR_ERR_WORKSPACE,
+                "gpr_predict_noalloc: ceil(n / %lld) * m = %lld partial sums exceed the fixed scratch of %lld",
+                (long long)kColsPerChunk, (long long)(nch * m), (long long)kScratchDoubles);
+  double* partial = nullptr;
+  HIPCHK(scratch_setup(&partial));
+  HIPCHK(launch_kmatvec_partial(Zs, m, Z, n, d, harg(h), alpha, partial, kColsPerChunk, st));
+  HIPCHK(launch_reduce_partials(partial, nch, m, 1.0, nullptr, 0.0, mean, st));
   return GPR_OK;
 }
 

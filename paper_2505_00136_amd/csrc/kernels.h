@@ -97,6 +97,12 @@ hipError_t launch_adam3(double* theta, double* state, const double* grad, double
                         double eps, int t0, int t1, int t2, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
 
+// scratch.hip: file-scope device array of kScratchDoubles float64 (the partial sums of the
+// allocation-free prediction); scratch_setup() looks up its address on the current device
+// (once per device, then cached) and returns it in *out (out may be null).
+constexpr int64_t kScratchDoubles = (int64_t)1 << 21;   // 16 MiB per device
+hipError_t scratch_setup(double** out);
+
 // warmstart.hip
 int64_t stats_sort_len(int64_t nsub);
 hipError_t launch_summary_stats(const double* Zraw, const double* Zstd, const double* yraw, int64_t n, int64_t d,
