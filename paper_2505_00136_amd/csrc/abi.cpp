@@ -333,6 +333,10 @@ void describe_transpose(Program& P, const TileLayout& L, void* K, int prec, cons
            {span(dst, bytes)});
 }
 
+// Split modes with a tile edge that is a multiple of 256: planes in the tiled layout and
+// the 256 x 256 update kernel; otherwise row-major planes and 128 x 128 macro tiles.
+bool bf16_tiled(const TileLayout& L) { return L.b % 256 == 0; }
+
 // hi/mid(/lo) bfloat16 planes of the solved panel k (split modes), buffer set k mod 2.
 void describe_split(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
   const int64_t b = L.b, T = L.T;
@@ -343,8 +347,11 @@ void describe_split(Program& P, const TileLayout& L, void* K, int prec, const Ch
   const int np = prec == GPR_BF16X6 ? 3 : 2;
   std::vector<Span> wr;
   for (int p = 0; p < np; ++p) wr.push_back(span(pl + p * pstride, count * 2));
+  const bool tiled = bf16_tiled(L);
   P.kernel([=](hipStream_t s) {
-    return launch_split_bf16x3(panel, count, pl, pl + pstride, prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr, s);
+    uint16_t* lo = prec == GPR_BF16X6 ? pl + 2 * pstride : nullptr;
+    return tiled ? launch_split_bf16x3_tiled(panel, count, b, pl, pl + pstride, lo, s)
+                 : launch_split_bf16x3(panel, count, pl, pl + pstride, lo, s);
   }, {span(panel, count * 4)}, wr);
 }
 
@@ -379,7 +386,10 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
     }
     P.gemm_end();
   }
-  const int kind = !split ? GEMM_KIND_UPDATE : (prec == GPR_BF16X6 ? GEMM_KIND_BF16X6 : GEMM_KIND_BF16X3);
+  const bool t256 = split && bf16_tiled(L);
+  const int kind = !split ? GEMM_KIND_UPDATE
+                          : (prec == GPR_BF16X6 ? (t256 ? GEMM_KIND_BF16X6_T256 : GEMM_KIND_BF16X6)
+                                                : (t256 ? GEMM_KIND_BF16X3_T256 : GEMM_KIND_BF16X3));
   P.gemm_begin(mixed, kind, mixed ? gemm_flops : syrk_flops + gemm_flops);
   for (int64_t nn = n0; nn < n1; ++nn) {
     for (int64_t m = nn; m < T; ++m) {

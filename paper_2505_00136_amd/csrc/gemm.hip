@@ -543,8 +543,10 @@ hipError_t launch_tiles_t(const GemmJob* jobs, const GemmSeg* segs, int njobs, i
 hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind, int spec,
                        hipStream_t st) {
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (kind == GEMM_KIND_BF16X3_T256 || kind == GEMM_KIND_BF16X6_T256)
+    return launch_gemm_bf16_t256(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
   if (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
-    return launch_gemm_bf16(kind == GEMM_KIND_BF16X6 ? 6 : 3, jobs, segs, njobs, nwg, st);
+    return launch_gemm_bf16(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
   if (kind == GEMM_KIND_TRACE) return hipErrorInvalidValue;   // launched by launch_gemm_trace
   if (kind == GEMM_KIND_WIDEN) {
     if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_KK>));

@@ -225,4 +225,239 @@ hipError_t launch_split_bf16x3(const float* x, int64_t count, void* hi, void* mi
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- 256 x 256 macro tiles
+//
+// The trailing update of tiles whose edge is a multiple of 256 uses planes in a tiled
+// layout and a larger macro tile.  Within each b x b tile of a plane, element (r, c) is at
+//   ((r / 256) (b / 16) + c / 16) 4096 + (r % 256) 16 + c % 16,
+// so a 256-row x 16-deep chunk is 8 KB of contiguous memory (fully coalesced loads; each
+// tile still occupies its b^2 elements, at the same offset as in the row-major layout).
+// A 512-thread workgroup (eight wave64s as 2 x 4, each 128 x 64) computes a 256 x 256
+// macro tile with v_mfma_f32_32x32x16_bf16 (4 x 2 accumulators of 32 x 32 per wave).
+// Chunks are 16 deep and double-buffered in LDS, one barrier per chunk.  LDS rows are 48
+// bytes (the 32 bytes of a chunk row and 16 of padding): the 16-byte fragment reads of
+// 16 consecutive lanes (rows r..r+15) then fall on 16 distinct 16-byte bank groups (with
+// unpadded 32-byte rows the counters showed bank conflicts on 37 % of the LDS cycles).  The planes of chunk c+2 are loaded into registers (a ring of two)
+// while chunk c is multiplied, so each load has two chunks' products to arrive: with one
+// workgroup per CU a single chunk of look-ahead left the matrix cores waiting on L2.
+// Against the 128 x 128 tiles above this halves the operand bytes per product fetched
+// from L2 and cuts the LDS fragment reads per product by a quarter.
+constexpr int BT_M = 256;                 // macro tile edge
+constexpr int BT_K = 16;                  // chunk depth
+constexpr int BT_PITCH = 24;              // bf16 elements per LDS row (48 bytes)
+constexpr int BT_THREADS = 512;
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+GPR_DEV v16f mma32_bf16(v8bf a, v8bf b, v16f c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+
+// hi + mid (+ lo) of float32 x, written in the tiled layout (tiles of edge b, b % 256 == 0).
+// Thread i produces output element i of each plane: element (r, c) of the source.
+__global__ void split_bf16x3_tiled_kernel(const float* __restrict__ x, int64_t count, int64_t b,
+                                          bfraw* __restrict__ hi, bfraw* __restrict__ mid, bfraw* __restrict__ lo) {
+  const int64_t bb = b * b, kc = b / BT_K;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < count; o += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = o / bb, rem = o % bb;
+    const int64_t blk = rem >> 12, within = rem & 4095;
+    const int64_t r = q * b + (blk / kc) * BT_M + (within >> 4);
+    const int64_t c = (blk % kc) * BT_K + (within & 15);
+    const float v = x[r * b + c];
+    const bfraw h = bf16_rne_bits(v);
+    const float r1 = v - bf16_to_float(h);
+    const bfraw m = bf16_rne_bits(r1);
+    const float r2 = r1 - bf16_to_float(m);
+    hi[o] = h;
+    mid[o] = m;
+    if (lo) lo[o] = bf16_rne_bits(r2);
+  }
+}
+
+template <int NP>
+struct BtRegs {
+  u32x4 a[NP], b[NP];
+};
+
+// This thread's 16 bytes of each plane of the chunk (row tid / 2, k half tid % 2).
+template <int NP>
+GPR_DEV void bt_load(const bfraw* A, const bfraw* B, int64_t pa, int64_t pb, int64_t offa, int64_t offb, int tid,
+                     BtRegs<NP>& r) {
+  typedef __attribute__((address_space(1))) const u32x4 gu4;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    r.a[p] = *(gu4*)(A + p * pa + offa + tid * 8);
+    r.b[p] = *(gu4*)(B + p * pb + offb + tid * 8);
+  }
+}
+
+template <int NP>
+GPR_DEV void bt_store(bfraw* As, bfraw* Bs, int tid, const BtRegs<NP>& r) {
+  const int off = (tid >> 1) * BT_PITCH + (tid & 1) * 8;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    *(u32x4*)(As + p * BT_M * BT_PITCH + off) = r.a[p];
+    *(u32x4*)(Bs + p * BT_M * BT_PITCH + off) = r.b[p];
+  }
+}
+
+GPR_DEV v8bf bt_frag(const bfraw* S, int plane, int row, int koff) {
+  const uint4 v = *(const uint4*)(S + (plane * BT_M + row) * BT_PITCH + koff);
+  return __builtin_bit_cast(v8bf, v);
+}
+
+// acc += the products of one LDS chunk (this wave's 128 x 64 block).  Rows are taken two
+// 32-row blocks at a time and each product type is issued for the four accumulators of
+// the pair before the next, so that consecutive matrix-core instructions do not depend on
+// each other.
+template <int NPROD, int NP>
+GPR_DEV void bt_mma(const bfraw* As, const bfraw* Bs, int wm, int wn, int frow, int fk, v16f (&acc)[4][2]) {
+  v8bf b[2][NP];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) b[j][p] = bt_frag(Bs, p, wn + j * 32 + frow, fk);
+#pragma unroll
+  for (int i0 = 0; i0 < 4; i0 += 2) {
+    v8bf a[2][NP];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) a[ii][p] = bt_frag(As, p, wm + (i0 + ii) * 32 + frow, fk);
+    // plane pairs (A, B), small products first: (mm, lh, hl), then (mh, hm), then hh
+    constexpr int NQ = NPROD == 6 ? 6 : 3;
+    constexpr int PA[6] = {1, 2, 0, 1, 0, 0}, PB[6] = {1, 0, 2, 0, 1, 0};
+#pragma unroll
+    for (int q = (NPROD == 6 ? 0 : 3); q < 6; ++q)
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i0 + ii][j] = mma32_bf16(a[ii][PA[q] % NP], b[j][PB[q] % NP], acc[i0 + ii][j]);
+    (void)NQ;
+  }
+}
+
+// NPROD = 3 (hh, hm, mh) or 6 (+ hl, lh, mm).  Every job covers whole 256 x 256 macro
+// tiles, every segment is a pair of tiled-layout planes (lda = ldb = K, a multiple of 16,
+// no triangular skips); the host checks this before the launch.
+template <int NPROD>
+__global__ __launch_bounds__(BT_THREADS, 1)
+void gemm_bf16x_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  constexpr int NP = NPROD == 6 ? 3 : 2;
+  constexpr int HALF = NP * BT_M * BT_PITCH;   // the A (then the B) planes of one chunk
+  __shared__ __align__(16) bfraw smem[2 * 2 * HALF];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int midj = (lo + hi + 1) >> 1;
+    if (jobs[midj].wg_begin <= bid) lo = midj; else hi = midj - 1;
+  }
+  const GemmJob job = jobs[lo];
+  int m0, n0;
+  {
+    const int t = bid - job.wg_begin, tn = job.tiles_n, tm = job.M / BT_M;
+    if ((tn & 7) == 0 && (tm & 7) == 0) {
+      const int sb = t >> 6, w = t & 63, sbn = tn >> 3;
+      m0 = ((sb / sbn) * 8 + (w >> 3)) * BT_M;
+      n0 = ((sb % sbn) * 8 + (w & 7)) * BT_M;
+    } else {
+      m0 = (t / tn) * BT_M;
+      n0 = (t % tn) * BT_M;
+    }
+  }
+  if ((job.flags & JOB_LOWER_ONLY) && (m0 + BT_M - 1 < n0)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+  const int frow = lane & 31, fk = (lane >> 5) * 8;
+
+  v16f acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  bfraw* const L0 = smem;              // chunk buffer 0: A planes, then B planes
+  bfraw* const L1 = smem + 2 * HALF;   // chunk buffer 1
+  bool primed = false;
+  for (int s = job.seg0; s < job.seg0 + job.nseg; ++s) {
+    const GemmSeg& sg = segs[s];
+    const int nck = sg.K / BT_K;
+    if (nck <= 0) continue;
+    const bfraw* A = (const bfraw*)sg.A;
+    const bfraw* B = (const bfraw*)sg.B;
+    const int64_t pa = sg.pstrideA, pb = sg.pstrideB;
+    // offsets of the macro tile's 256-row blocks: chunk c is at + c 4096
+    const int64_t offa = (int64_t)(m0 / BT_M) * (sg.lda / BT_K) * 4096;
+    const int64_t offb = (int64_t)(n0 / BT_M) * (sg.ldb / BT_K) * 4096;
+    // chunk q lives in registers r[q % 2] until it is stored into LDS buffer q % 2
+    BtRegs<NP> r0, r1;
+    bt_load<NP>(A, B, pa, pb, offa, offb, tid, r0);
+    if (nck > 1) bt_load<NP>(A, B, pa, pb, offa + 4096, offb + 4096, tid, r1);
+    if (primed) __syncthreads();   // the previous segment's last chunk has been read
+    bt_store<NP>(L0, L0 + HALF, tid, r0);
+    __syncthreads();
+    primed = true;
+    for (int c = 0; c < nck; c += 2) {
+      // even chunk c from buffer 0; chunk c+1 waits in r1, chunk c+2 is loaded into r0
+      if (c + 2 < nck) bt_load<NP>(A, B, pa, pb, offa + (int64_t)(c + 2) * 4096, offb + (int64_t)(c + 2) * 4096, tid, r0);
+      bt_mma<NPROD, NP>(L0, L0 + HALF, wm, wn, frow, fk, acc);
+      if (c + 1 >= nck) break;
+      __builtin_amdgcn_sched_barrier(0);
+      bt_store<NP>(L1, L1 + HALF, tid, r1);
+      __syncthreads();
+      // odd chunk c+1 from buffer 1; chunk c+2 waits in r0, chunk c+3 is loaded into r1
+      if (c + 3 < nck) bt_load<NP>(A, B, pa, pb, offa + (int64_t)(c + 3) * 4096, offb + (int64_t)(c + 3) * 4096, tid, r1);
+      bt_mma<NPROD, NP>(L1, L1 + HALF, wm, wn, frow, fk, acc);
+      if (c + 2 >= nck) break;
+      __builtin_amdgcn_sched_barrier(0);
+      bt_store<NP>(L0, L0 + HALF, tid, r0);
+      __syncthreads();
+    }
+  }
+
+  // 32 x 32 f32 output: lane l, register r holds column l % 32, row 8 (r / 4) + 4 (l / 32) + r % 4
+  const bool c32 = job.flags & JOB_C_F32;
+  const double alpha = job.alpha, beta = job.beta;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = n0 + wn + j * 32 + (lane & 31);
+        double v = alpha * (double)acc[i][j][r];
+        if (c32) {
+          if (beta != 0.0) v += beta * (double)((const float*)job.Cin)[(int64_t)row * job.ldcin + col];
+          ((float*)job.C)[(int64_t)row * job.ldc + col] = (float)v;
+        } else {
+          if (beta != 0.0) v += beta * ((const double*)job.Cin)[(int64_t)row * job.ldcin + col];
+          ((double*)job.C)[(int64_t)row * job.ldc + col] = v;
+        }
+      }
+}
+
+hipError_t launch_gemm_bf16_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                                 hipStream_t st) {
+  if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (nprod == 6)
+    hipLaunchKernelGGL(gemm_bf16x_t256_kernel<6>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs);
+  else
+    hipLaunchKernelGGL(gemm_bf16x_t256_kernel<3>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_bf16x3_tiled(const float* x, int64_t count, int64_t b, void* hi, void* mid, void* lo,
+                                     hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (b % BT_M != 0 || count % (b * b) != 0) return hipErrorInvalidValue;
+  int64_t g = (count + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(split_bf16x3_tiled_kernel, dim3((unsigned)g), dim3(256), 0, st, x, count, b, (bfraw*)hi,
+                     (bfraw*)mid, (bfraw*)lo);
+  return hipGetLastError();
+}
+
 }  // namespace gpr

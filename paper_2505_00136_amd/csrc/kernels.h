@@ -11,7 +11,21 @@ namespace gpr {
 // float64 products; BF16X3/X6: split-bfloat16 products of bfloat16 planes.
 enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_KIND_BF16X6 = 3, GEMM_KIND_WIDEN = 4,
        GEMM_KIND_TRTRI = 5,    // triangular-inverse steps of the gradient (own kernel symbol)
-       GEMM_KIND_TRACE = 6 };  // K^{-1} products fused with the gradient reduction (launch_gemm_trace)
+       GEMM_KIND_TRACE = 6,    // K^{-1} products fused with the gradient reduction (launch_gemm_trace)
+       // split-bfloat16 update on 256 x 256 macro tiles from planes in the tiled layout
+       // (gemm_bf16.hip; tiles whose edge is a multiple of 256)
+       GEMM_KIND_BF16X3_T256 = 7, GEMM_KIND_BF16X6_T256 = 8 };
+inline bool gemm_kind_bf16(int kind) {
+  return kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6 || kind == GEMM_KIND_BF16X3_T256 ||
+         kind == GEMM_KIND_BF16X6_T256;
+}
+inline int gemm_kind_nprod(int kind) {
+  return (kind == GEMM_KIND_BF16X6 || kind == GEMM_KIND_BF16X6_T256) ? 6 : 3;
+}
+// macro tile edge of a launch of this kind (the workgroup count of each job follows from it)
+inline int gemm_kind_macro(int kind) {
+  return (kind == GEMM_KIND_BF16X3_T256 || kind == GEMM_KIND_BF16X6_T256) ? 256 : GEMM_BM;
+}
 // spec: main-loop specialisation from gemm_launch_spec (host tables of the launch)
 hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind, int spec,
                        hipStream_t st);
@@ -27,6 +41,13 @@ int gemm_launch_spec(const GemmJob* jobs, int njobs, const GemmSeg* segs, int es
 hipError_t launch_gemm_bf16(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, hipStream_t st);
 // hi/mid/lo bfloat16 parts (round to nearest even) of float32 x; lo may be null
 hipError_t launch_split_bf16x3(const float* x, int64_t count, void* hi, void* mid, void* lo, hipStream_t st);
+// the same for b x b row-major tiles (count a multiple of b^2, b % 256 == 0), the parts
+// written in the tiled layout of the 256 x 256 update kernel
+hipError_t launch_split_bf16x3_tiled(const float* x, int64_t count, int64_t b, void* hi, void* mid, void* lo,
+                                     hipStream_t st);
+// the update on 256 x 256 macro tiles (jobs of whole macro tiles, tiled-layout planes)
+hipError_t launch_gemm_bf16_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                                 hipStream_t st);
 
 // potrf_block.hip: Cholesky + inverse of one jb x jb (jb <= 64) diagonal block by one workgroup
 hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,

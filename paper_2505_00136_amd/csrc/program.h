@@ -85,7 +85,7 @@ struct Program {
   const GemmSeg* dsegs = nullptr;
   hipError_t err = hipSuccess;
   int64_t gemm_flops_wg = 0;   // workgroups launched (statistics)
-  int job0 = 0, nwg = 0, f32 = 0, kind = 0;
+  int job0 = 0, nwg = 0, f32 = 0, kind = 0, mt = GEMM_BM;   // mt: macro tile edge of the open launch
   double kind_flops = 0.0;
   bool cur_valid = false;
   // gradient-trace launches: arguments, and running count of their workgroups (each writes
@@ -123,6 +123,7 @@ struct Program {
     nwg = 0;
     f32 = use_f32;
     kind = launch_kind;
+    mt = gemm_kind_macro(launch_kind);
     kind_flops = algo_flops;
   }
   // Adds a job C[M x N] = alpha * sum(segments added next) + beta * Cin.
@@ -140,13 +141,13 @@ struct Program {
     j.seg0 = (int32_t)segs.size();
     j.nseg = 0;
     j.wg_begin = nwg;
-    j.tiles_n = (int32_t)ceil_div(N, GEMM_BN);
+    j.tiles_n = (int32_t)ceil_div(N, mt);
     j.flags = flags;
     j.aux0 = aux0;
     j.aux1 = aux1;
     cur_valid = M > 0 && N > 0;
     if (!cur_valid) return;
-    const int64_t tiles = ceil_div(M, GEMM_BM) * (int64_t)j.tiles_n;
+    const int64_t tiles = ceil_div(M, mt) * (int64_t)j.tiles_n;
     jobs.push_back(j);
     nwg += (int)tiles;
   }
@@ -171,8 +172,7 @@ struct Program {
     gemm_flops_wg += nwg;
     hipEvent_t ea = nullptr, eb = nullptr;
     bool timed = false;
-    if (kind == GEMM_KIND_UPDATE || kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6 ||
-        kind == GEMM_KIND_TRTRI || kind == GEMM_KIND_TRACE) {
+    if (kind == GEMM_KIND_UPDATE || gemm_kind_bf16(kind) || kind == GEMM_KIND_TRTRI || kind == GEMM_KIND_TRACE) {
       std::lock_guard<std::mutex> lk(g_timing.mu);
       if (g_timing.on) {
         ea = g_timing.get();
@@ -181,14 +181,30 @@ struct Program {
       }
     }
     hipStream_t sx = stream();
+    if (gemm_kind_macro(kind) == 256) {
+      // the 256 x 256 kernel has no bounds checks: whole macro tiles, 16-deep chunks and
+      // tiled-layout planes whose row length is the segment depth
+      for (int jx = job0; jx < job0 + nj; ++jx) {
+        const GemmJob& J = jobs[jx];
+        bool ok = J.M % 256 == 0 && J.N % 256 == 0;
+        for (int sx2 = J.seg0; ok && sx2 < J.seg0 + J.nseg; ++sx2) {
+          const GemmSeg& S = segs[sx2];
+          ok = S.K % 16 == 0 && S.lda == S.K && S.ldb == S.K && S.modeA == MODE_KC && S.modeB == MODE_KC &&
+               S.tri == 0;
+        }
+        if (!ok) {
+          err = hipErrorInvalidValue;
+          return;
+        }
+      }
+    }
     if (kind == GEMM_KIND_TRACE && (!trace || trace_wg + nwg > trace_cap)) {
       err = hipErrorInvalidValue;
       return;
     }
     const int esize = (f32 || kind == GEMM_KIND_WIDEN) ? 4 : 8;
     const int bk = 16;   // chunk depth of the main loop (both product types)
-    const int spec = (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
-                         ? -1 : gemm_launch_spec(jobs.data() + job0, nj, segs.data(), esize, bk);
+    const int spec = gemm_kind_bf16(kind) ? -1 : gemm_launch_spec(jobs.data() + job0, nj, segs.data(), esize, bk);
     if (timed) (void)hipEventRecord(ea, sx);
     if (kind == GEMM_KIND_TRACE) {
       TraceArgs ta = *trace;
@@ -202,8 +218,7 @@ struct Program {
       (void)hipEventRecord(eb, sx);
       std::lock_guard<std::mutex> lk(g_timing.mu);
       int tk = f32 ? 1 : 0;
-      if (kind == GEMM_KIND_BF16X3) tk = 2;
-      else if (kind == GEMM_KIND_BF16X6) tk = 3;
+      if (gemm_kind_bf16(kind)) tk = gemm_kind_nprod(kind) == 6 ? 3 : 2;
       else if (kind == GEMM_KIND_TRTRI) tk = f32 ? 5 : 4;
       else if (kind == GEMM_KIND_TRACE) tk = f32 ? 7 : 6;
       g_timing.recs.push_back({ea, eb, kind_flops, tk});
@@ -230,9 +245,9 @@ struct Program {
   // extents of its segments (all planes in the split modes).
   void log_gemm(int nj) {
     AccessLog::Op op{AccessLog::LAUNCH, cur, -1, {}, {}};
-    const bool split = kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6;
+    const bool split = gemm_kind_bf16(kind);
     const int oe = split ? 2 : ((f32 || kind == GEMM_KIND_WIDEN) ? 4 : 8);
-    const int planes = kind == GEMM_KIND_BF16X6 ? 3 : (kind == GEMM_KIND_BF16X3 ? 2 : 1);
+    const int planes = split ? (gemm_kind_nprod(kind) == 6 ? 3 : 2) : 1;
     for (int jx = job0; jx < job0 + nj; ++jx) {
       const GemmJob& J = jobs[jx];
       const int ce = (J.flags & JOB_C_F32) ? 4 : 8;
