@@ -119,10 +119,28 @@ GPR_API const char* gpr_last_error(void);
  * what it lacks.  Host only; may be called again (it only grows the resources). */
 GPR_API int gpr_init(int64_t n, int64_t m, int64_t tile, int prec);
 
-/* Schedule of gpr_cholesky, process-wide: on != 0 (the default) factors diagonal tile
- * k+1 and its panel on the auxiliary stream while step k's remaining update runs on the
- * caller's stream; 0 issues every launch on the caller's stream.  Both give the same
- * bits.  Host only; takes effect for factorisations issued afterwards. */
+/* Schedules of the tiled factorisation (gpr_set_schedule); all give the same bits.
+ *  GPR_SCHEDULE_STREAM:    every launch on the caller's stream, in the order of Fig. 1.
+ *  GPR_SCHEDULE_LOOKAHEAD: (the default) diagonal tile k+1 and its panel are factored on an
+ *                          auxiliary stream while step k's remaining update runs on the
+ *                          caller's stream, events ordering the two.
+ *  GPR_SCHEDULE_DEVICE:    the tasks of Fig. 1 (and the block steps inside the diagonal
+ *                          tiles) form a graph whose edges are their tile dependencies
+ *                          (Section 4.2's dataflow), executed by one persistent kernel: a
+ *                          task whose predecessors have finished enters a ready queue (the
+ *                          critical path first) and workgroups take its work items, the
+ *                          dependencies being resolved by per-task counters on the device
+ *                          (in place of the futures of Section 3.1).  GPR_FP64 only; the
+ *                          other precisions use the look-ahead.  When no task finishes for
+ *                          10 s the run gives up: gpr_cholesky then reports GPR_ERR_HIP when
+ *                          `info` is requested. */
+enum gpr_schedule { GPR_SCHEDULE_STREAM = 0, GPR_SCHEDULE_LOOKAHEAD = 1, GPR_SCHEDULE_DEVICE = 2 };
+
+/* Schedule of gpr_cholesky (a gpr_schedule), process-wide, for factorisations issued
+ * afterwards.  Host only.  Errors: GPR_ERR_ARG for an unknown schedule. */
+GPR_API int gpr_set_schedule(int mode);
+
+/* gpr_set_schedule(on ? GPR_SCHEDULE_LOOKAHEAD : GPR_SCHEDULE_STREAM). */
 GPR_API int gpr_set_lookahead(int on);
 
 /* Bytes of the tiled matrix of an n x n covariance with tile edge `tile` in precision `prec`
@@ -305,6 +323,20 @@ GPR_API int gpr_timing_enable(int on);
  *        two triangular tiles; all launches of one gradient add up to about n^3 / 3).
  * Resets that kind's record.  All three are host outputs. */
 GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops);
+
+/* Host model of the device task-graph schedule (GPR_SCHEDULE_DEVICE), host only: builds the
+ * graph that gpr_cholesky executes for (n, tile) in float64 (symbolic addresses) and runs
+ * the executor's claim / wait / finish code with `threads` host threads in place of
+ * workgroups, each item checking that every predecessor task has finished.  A task index
+ * withhold >= 0 gets one predecessor more than it has, so its wait can never end: the
+ * waits must then give up after limit_ms and every thread return.  withhold <= -2 drops
+ * edge number -2 - withhold (in successor-list order) before the checks.  report[0..8] (host
+ * array of 9): tasks, items, edges, items run, violations (items that started before a
+ * predecessor finished, and items that did not run exactly once; 0 for a correct graph
+ * and executor), abort flag, threads that gave up, threads that returned, and pairs of
+ * tasks whose byte ranges overlap with one writing but that no path of edges orders (0 for
+ * a correct graph; -1 when the graph has over 4096 tasks). */
+GPR_API int gpr_dag_check(int64_t n, int64_t tile, int threads, int64_t withhold, double limit_ms, int64_t* report);
 
 /* Task census of the tiled Cholesky with T tiles per dimension as scheduled by this
  * library (Fig. 1): counts[0..3] = POTRF, TRSM, SYRK, GEMM tile tasks.  Host only. */

@@ -38,6 +38,8 @@ _SIGS = {
     "gpr_last_error": ([], ctypes.c_char_p),
     "gpr_init": ([_i64, _i64, _i64, _int], _int),
     "gpr_set_lookahead": ([_int], _int),
+    "gpr_set_schedule": ([_int], _int),
+    "gpr_dag_check": ([_i64, _i64, _int, _i64, _dbl, ctypes.POINTER(_i64)], _int),
     "gpr_tiles_bytes": ([_i64, _i64, _int, ctypes.POINTER(_sz)], _int),
     "gpr_workspace_size": ([_i64, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)], _int),
     "gpr_assemble": ([_vp, _i64, _i64, GprHyper, _i64, _int, _vp, _vp], _int),
@@ -147,6 +149,24 @@ def gpr_init(n=0, m=0, tile=1, prec="fp64"):
 
 def gpr_set_lookahead(on: bool):
     _check(load().gpr_set_lookahead(int(on)))
+
+
+SCHEDULES = {"stream": 0, "lookahead": 1, "device": 2}
+
+
+def gpr_set_schedule(mode):
+    """'stream', 'lookahead' (the default) or 'device' (the task graph on the device)."""
+    _check(load().gpr_set_schedule(SCHEDULES[mode] if isinstance(mode, str) else int(mode)))
+
+
+DAG_REPORT = ("tasks", "items", "edges", "items_run", "violations", "aborted", "timed_out", "threads_returned",
+              "unordered_conflicts")
+
+
+def gpr_dag_check(n, tile, threads, withhold=-1, limit_ms=1000.0):
+    r = (_i64 * 9)()
+    _check(load().gpr_dag_check(n, tile, threads, withhold, limit_ms, r))
+    return dict(zip(DAG_REPORT, list(r)))
 
 
 def gpr_tiles_bytes(n, tile, prec) -> int:

@@ -9,8 +9,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <unordered_map>
 #include <mutex>
 #include <string>
+#include <chrono>
+#include <thread>
 #include <vector>
 
 #include "gpr.h"
@@ -130,6 +134,7 @@ struct DevRes {
   std::vector<hipEvent_t> events;
   StageSlot slot[kStageSlots];
   int next = 0;
+  int dag_slots = 0;    // workgroups of the task-graph executor that fit at once (0: not queried yet)
 };
 DevRes g_res[kMaxDevices];
 
@@ -199,6 +204,38 @@ int upload_tables(const Program& P, void* arena, size_t cap, hipStream_t st, con
   return GPR_OK;
 }
 
+// Uploads host arrays into `arena`, each at a 256-byte boundary, through the next staging
+// slot (one copy); their device addresses are returned in `dev`.
+int upload_parts(const std::vector<std::pair<const void*, size_t>>& parts, void* arena, size_t cap, hipStream_t st,
+                 std::vector<void*>& dev) {
+  std::vector<size_t> off;
+  size_t bytes = 0;
+  for (const auto& p : parts) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    off.push_back(bytes);
+    bytes += p.second;
+  }
+  if (bytes + 1024 > cap) return fail(GPR_ERR_WORKSPACE, "table arena too small (%zu > %zu)", bytes + 1024, cap);
+  dev.clear();
+  for (size_t o : off) dev.push_back((char*)arena + o);
+  if (bytes == 0) return GPR_OK;
+  DevRes* R = nullptr;
+  int rc = current_res(&R);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(R->mu);
+  if (R->slot[R->next].cap < bytes && (rc = grow_slots(R, bytes * 2))) return rc;
+  StageSlot& s = R->slot[R->next];
+  R->next = (R->next + 1) % kStageSlots;
+  if (!s.ev) HIPCHK(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+  if (s.inflight) HIPCHK(hipEventSynchronize(s.ev));   // the ring wrapped onto a copy still queued
+  for (size_t i = 0; i < parts.size(); ++i)
+    if (parts[i].second) memcpy(s.host + off[i], parts[i].first, parts[i].second);
+  HIPCHK(hipMemcpyAsync(arena, s.host, bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(s.ev, st));
+  s.inflight = true;
+  return GPR_OK;
+}
+
 // Auxiliary stream and events of the look-ahead on the current device.
 int aux_resources(int nevents, hipStream_t* aux, std::vector<hipEvent_t>** evs) {
   DevRes* R = nullptr;
@@ -247,6 +284,8 @@ struct CholWs {
   float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
   uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2, two sets
   void* panel_t;    // transposed tiles of the solved panel (other modes), (T-1) b^2 elements, two sets
+  int32_t* dag_state;   // task-graph schedule (float64): per-task counters and the control words
+  int64_t dag_ntasks;
 
   void* arena;
   size_t arena_cap;
@@ -257,12 +296,19 @@ void describe_diag(Program& P, const TileLayout& L, void* K, const CholWs& w, in
   const int64_t b = L.b;
   double* Dk = L.diag(K, k);
   double* Wk = L.winv(K, k);
-  P.kernel([=](hipStream_t s) { return launch_set_identity(Wk, b, s); }, {}, {span(Wk, b * b * 8)});
+  const int64_t fill_items = ceil_div(b * b, DAG_ELEMS_PER_ITEM);
+  P.op(DAG_IDENTITY, DagOp{Wk, nullptr, b, 0, 0, 0}, fill_items,
+       [=](hipStream_t s) { return launch_set_identity(Wk, b, s); }, {}, {span(Wk, b * b * 8)});
   const int64_t nbk = kInnerBlock;
   for (int64_t r0 = 0; r0 < b; r0 += nbk) {
     const int64_t jb = std::min(nbk, b - r0), rb = r0 + jb, nbelow = b - rb;
-    P.kernel([=](hipStream_t s) { return launch_potrf_block(Dk + r0 * b + r0, b, Wk + r0 * b + r0, b, (int)jb, k * b + r0, w.info, s); },
-             {}, {span2d(Dk + r0 * b + r0, jb, jb, b, 8), span2d(Wk + r0 * b + r0, jb, jb, b, 8), span(w.info, 8)});
+    // (the first failing pivot is an atomic minimum, which needs no ordering: the task form
+    // leaves the info word out of its access ranges)
+    std::vector<Span> pw{span2d(Dk + r0 * b + r0, jb, jb, b, 8), span2d(Wk + r0 * b + r0, jb, jb, b, 8)};
+    if (!P.dagr) pw.push_back(span(w.info, 8));
+    P.op(DAG_POTRF, DagOp{Dk + r0 * b + r0, Wk + r0 * b + r0, b, jb, k * b + r0, 0}, 1,
+         [=](hipStream_t s) { return launch_potrf_block(Dk + r0 * b + r0, b, Wk + r0 * b + r0, b, (int)jb, k * b + r0, w.info, s); },
+         {}, pw);
     P.gemm_begin(0);
     // block row j of W: W_j[:, 0:r0] <- W_jj W_j[:, 0:r0]  (in place, column-partitioned)
     P.job(Wk + r0 * b, b, nullptr, 0, jb, r0, 1.0, 0.0, 0);
@@ -282,7 +328,8 @@ void describe_diag(Program& P, const TileLayout& L, void* K, const CholWs& w, in
       P.gemm_end();
     }
   }
-  P.kernel([=](hipStream_t s) { return launch_zero_upper(Dk, b, s); }, {}, {span(Dk, b * b * 8)});
+  P.op(DAG_ZERO_UPPER, DagOp{Dk, nullptr, b, 0, 0, 0}, fill_items,
+       [=](hipStream_t s) { return launch_zero_upper(Dk, b, s); }, {}, {span(Dk, b * b * 8)});
 }
 
 // Inputs of the TRSM of panel k (block column k below the diagonal): a copy of the panel
@@ -292,8 +339,10 @@ void describe_panel_copy(Program& P, const TileLayout& L, void* K, int prec, con
   if (k >= T - 1) return;
   const void* panel = L.off(K, k + 1, k);
   const size_t pbytes = (size_t)(T - k - 1) * b * b * L.esize;
-  P.kernel([=](hipStream_t s) { return launch_copy(w.panel, panel, pbytes, s); }, {span(panel, pbytes)},
-           {span(w.panel, pbytes)});
+  if (P.dagr && ((((uintptr_t)w.panel) | (uintptr_t)panel | pbytes) & 15)) P.dagr->ok = false;
+  P.op(DAG_COPY, DagOp{w.panel, panel, (int64_t)pbytes, 0, 0, 0}, ceil_div((int64_t)pbytes, DAG_COPY_BYTES_PER_ITEM),
+       [=](hipStream_t s) { return launch_copy(w.panel, panel, pbytes, s); }, {span(panel, pbytes)},
+       {span(w.panel, pbytes)});
   if (is_mixed(prec)) {
     const double* Wk = L.winv(K, k);
     P.kernel([=](hipStream_t s) { return launch_convert_f64_f32(Wk, w.w32, b * b, s); }, {span(Wk, b * b * 8)},
@@ -329,8 +378,10 @@ void describe_transpose(Program& P, const TileLayout& L, void* K, int prec, cons
   const int64_t count = T - k - 1;
   const int es = L.esize;
   const size_t bytes = (size_t)count * b * b * es;
-  P.kernel([=](hipStream_t s) { return launch_transpose_tiles(panel, dst, b, count, es, s); }, {span(panel, bytes)},
-           {span(dst, bytes)});
+  const int64_t nbt = ceil_div(b, 64);
+  P.op(DAG_TRANSPOSE, DagOp{dst, panel, b, count, es, 0}, count * nbt * nbt,
+       [=](hipStream_t s) { return launch_transpose_tiles(panel, dst, b, count, es, s); }, {span(panel, bytes)},
+       {span(dst, bytes)});
 }
 
 // Split modes with a tile edge that is a multiple of 256: planes in the tiled layout and
@@ -434,9 +485,11 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // diagonal block; that update shares its launch with the trailing update P_j P_j^T.
 int chol_events_needed(int64_t T) { return 1 + 2 * (int)T; }
 
-// The look-ahead is on unless gpr_set_lookahead(0) puts every launch on the caller's
-// stream (the two schedules give the same bits).
-std::atomic<int> g_lookahead{1};
+// Schedule of the factorisation (gpr_set_schedule): GPR_SCHEDULE_STREAM (every launch on the
+// caller's stream), GPR_SCHEDULE_LOOKAHEAD (two streams, the default) or GPR_SCHEDULE_DEVICE
+// (the task graph executed by a persistent kernel; float64 only, other precisions use the
+// look-ahead).  All give the same bits.
+std::atomic<int> g_schedule{GPR_SCHEDULE_LOOKAHEAD};
 
 void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, bool lookahead) {
   const int64_t T = L.T;
@@ -490,6 +543,120 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
            {span(info, 16)}, {span(info + 2, 16)});
 }
 
+// The factorisation as a task graph: the one-stream order of describe_cholesky with the
+// trailing update of each step split into one task per block column, so that the
+// dependencies, not the issue order, decide what overlaps (the next diagonal tile may
+// start once its own column is updated, any later column's update once its inputs are
+// ready).  The pivot word is reset before and copied after the graph, on the stream.
+void describe_cholesky_graph(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w) {
+  const int64_t T = L.T;
+  for (int64_t k = 0; k < T; ++k) {
+    // the critical path -- diagonal tile, panel, the next block column's update -- is
+    // served first from the first ready queue
+    if (P.dagr) P.dagr->prio = 0;
+    describe_diag(P, L, K, w, k);
+    describe_panel_copy(P, L, K, prec, w, k);
+    if (k < T - 1) {
+      P.gemm_begin(is_mixed(prec));
+      add_trsm_job(P, L, K, prec, w, k);
+      P.gemm_end();
+    }
+    describe_transpose(P, L, K, prec, w, k);
+    describe_split(P, L, K, prec, w, k);
+    for (int64_t c = k + 1; c < T; ++c) {
+      if (P.dagr) P.dagr->prio = c == k + 1 ? 0 : 1;
+      describe_update(P, L, K, prec, w, k, c, c + 1);
+    }
+  }
+}
+
+// Successor lists of a recorded graph.  Task u precedes task t (u issued first) when t
+// reads what u writes, writes what u reads or writes what u writes, at a granularity of
+// 1 MiB (coarser ranges only add edges).  Returns false when the edges exceed `max_succ`.
+constexpr int kDagGranuleShift = 20;
+
+bool dag_edges(DagRecord& R, std::vector<int32_t>& succ, size_t max_succ) {
+  struct Gran {
+    int32_t writer = -1;
+    std::vector<int32_t> readers;
+  };
+  const int nt = (int)R.tasks.size();
+  std::unordered_map<uint64_t, Gran> g;
+  g.reserve(1 << 16);
+  std::vector<std::vector<int32_t>> preds(nt);
+  std::vector<int32_t> stamp(nt, -1);
+  for (int t = 0; t < nt; ++t) {
+    auto add = [&](int32_t u) {
+      if (u >= 0 && u != t && stamp[u] != t) {
+        stamp[u] = t;
+        preds[t].push_back(u);
+      }
+    };
+    for (const Span& sp : R.rd[t]) {
+      if (sp.hi <= sp.lo) continue;
+      for (uint64_t q = sp.lo >> kDagGranuleShift; q <= (sp.hi - 1) >> kDagGranuleShift; ++q) {
+        Gran& e = g[q];
+        add(e.writer);
+        if (e.readers.empty() || e.readers.back() != t) e.readers.push_back(t);
+      }
+    }
+    for (const Span& sp : R.wr[t]) {
+      if (sp.hi <= sp.lo) continue;
+      for (uint64_t q = sp.lo >> kDagGranuleShift; q <= (sp.hi - 1) >> kDagGranuleShift; ++q) {
+        Gran& e = g[q];
+        add(e.writer);
+        for (int32_t r : e.readers) add(r);
+        e.writer = t;
+        e.readers.clear();
+      }
+    }
+  }
+  std::vector<int32_t> nsucc(nt, 0);
+  size_t edges = 0;
+  for (int t = 0; t < nt; ++t) {
+    R.tasks[t].npred = (int32_t)preds[t].size();
+    for (int32_t u : preds[t]) ++nsucc[u];
+    edges += preds[t].size();
+  }
+  if (edges > max_succ) return false;
+  int32_t off = 0;
+  for (int t = 0; t < nt; ++t) {
+    R.tasks[t].succ0 = off;
+    R.tasks[t].nsucc = 0;
+    off += nsucc[t];
+  }
+  succ.assign(edges, 0);
+  for (int t = 0; t < nt; ++t)
+    for (int32_t u : preds[t]) succ[R.tasks[u].succ0 + R.tasks[u].nsucc++] = t;
+  return true;
+}
+
+// Table bytes of a graph with nt tasks, ns successor entries and no ops, beyond the jobs.
+size_t dag_max_succ(size_t ntasks) { return 16 * ntasks + 1024; }
+size_t dag_table_bytes(const Program& P, const DagRecord& R) {
+  auto r256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return r256(P.jobs.size() * sizeof(GemmJob)) + r256(P.segs.size() * sizeof(GemmSeg)) +
+         r256(R.tasks.size() * sizeof(DagTask)) + r256(dag_max_succ(R.tasks.size()) * sizeof(int32_t)) +
+         r256(R.ops.size() * sizeof(DagOp)) + 1024;
+}
+
+// Number of tasks of the float64 graph of a layout (recorded once per (n, b), then cached).
+int64_t dag_task_count(const TileLayout& L) {
+  static std::mutex mu;
+  static std::map<std::pair<int64_t, int64_t>, int64_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({L.n, L.b});
+  if (it != cache.end()) return it->second;
+  Program P;
+  DagRecord R;
+  P.dagr = &R;
+  CholWs w{};
+  describe_cholesky_graph(P, L, nullptr, GPR_FP64, w);
+  const int64_t nt = (int64_t)R.tasks.size();
+  cache[{L.n, L.b}] = nt;
+  return nt;
+}
+
 struct CholSizes {
   size_t fixed, arena;
 };
@@ -505,7 +672,17 @@ CholSizes chol_sizes(const TileLayout& L, int prec) {
   CholWs w{};
   describe_cholesky(P1, L, nullptr, prec, w, false);
   describe_cholesky(P2, L, nullptr, prec, w, true);
-  return CholSizes{c.off, std::max(arena_bytes_of(P1), arena_bytes_of(P2))};
+  size_t arena = std::max(arena_bytes_of(P1), arena_bytes_of(P2));
+  if (prec == GPR_FP64) {
+    // the task graph's tables and its per-task counters
+    Program P3;
+    DagRecord R;
+    P3.dagr = &R;
+    describe_cholesky_graph(P3, L, nullptr, prec, w);
+    arena = std::max(arena, dag_table_bytes(P3, R));
+    c.take<int32_t>(dag_state_ints(dag_task_count(L)));
+  }
+  return CholSizes{c.off, arena};
 }
 
 CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
@@ -516,6 +693,10 @@ CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.b * L.b) : nullptr;
   w.planes = is_bf16(prec) ? c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b) : nullptr;
   w.panel_t = is_bf16(prec) ? nullptr : c.take<char>((size_t)2 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
+  if (prec == GPR_FP64) {
+    w.dag_ntasks = dag_task_count(L);
+    w.dag_state = c.take<int32_t>(dag_state_ints(w.dag_ntasks));
+  }
   w.arena = c.take<char>(0);
   w.arena_cap = ws_bytes > c.off ? ws_bytes - c.off : 0;
   return w;
@@ -849,6 +1030,27 @@ size_t optimize_state_bytes(int64_t n, int steps) {
   return c.off + 256;
 }
 
+// The executor's scheduling code on the host (gpr_dag_check): the atomics are the
+// compiler's, the clock counts nanoseconds, a wait yields the thread.
+struct DagHostOps {
+  static int fetch_add_relaxed(int32_t* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+  static int fetch_add_acq_rel(int32_t* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_ACQ_REL); }
+  static int fetch_add_release(int32_t* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_RELEASE); }
+  static int load_acquire(int32_t* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+  static int load_relaxed(int32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+  static void fence_acquire() { __atomic_thread_fence(__ATOMIC_ACQUIRE); }
+  static void store_release(int32_t* p, int v) { __atomic_store_n(p, v, __ATOMIC_RELEASE); }
+  static void cas_relaxed(int32_t* p, int expected, int desired) {
+    __atomic_compare_exchange_n(p, &expected, desired, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED);
+  }
+  static uint64_t clock() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+  }
+  static void pause() { std::this_thread::yield(); }
+};
+typedef DagCore<DagHostOps> HostCore;
+
 // Largest job-table upload of any call on a problem of this size (staging slot size).
 size_t table_bytes(const TileLayout& L, int64_t m, int prec) {
   size_t t = chol_sizes(L, prec).arena;
@@ -876,12 +1078,55 @@ size_t chol_ws_bytes(const TileLayout& L, int prec) {
   return s.fixed + 256 + s.arena;
 }
 
+// The task-graph executor gives up when no task has finished for this long.
+constexpr double kDagWaitLimitSeconds = 10.0;
+
+// The factorisation as a task graph on the device; *ran = false when this problem has no
+// task form (the caller then uses the streams).
+int chol_graph(void* K, const TileLayout& L, int prec, const CholWs& w, hipStream_t st, bool* ran) {
+  *ran = false;
+  Program P;
+  DagRecord R;
+  P.dagr = &R;
+  describe_cholesky_graph(P, L, K, prec, w);
+  if (!R.ok || R.tasks.empty() || (int64_t)R.tasks.size() > w.dag_ntasks) return GPR_OK;
+  std::vector<int32_t> succ;
+  if (!dag_edges(R, succ, dag_max_succ(R.tasks.size()))) return GPR_OK;
+  DevRes* D = nullptr;
+  int rc = current_res(&D);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(D->mu);
+    if (D->dag_slots <= 0) HIPCHK(dag_slots(&D->dag_slots));
+  }
+  std::vector<void*> dev;
+  rc = upload_parts({{P.jobs.data(), P.jobs.size() * sizeof(GemmJob)}, {P.segs.data(), P.segs.size() * sizeof(GemmSeg)},
+                     {R.tasks.data(), R.tasks.size() * sizeof(DagTask)}, {succ.data(), succ.size() * sizeof(int32_t)},
+                     {R.ops.data(), R.ops.size() * sizeof(DagOp)}},
+                    w.arena, w.arena_cap, st, dev);
+  if (rc) return rc;
+  const int nt = (int)R.tasks.size();
+  unsigned long long* info = w.info;
+  HIPCHK(launch_fill_u64(info, ~0ull, 2, st));
+  HIPCHK(launch_dag((const DagTask*)dev[2], nt, (const int32_t*)dev[3], (const DagOp*)dev[4], (const GemmJob*)dev[0],
+                    (const GemmSeg*)dev[1], w.dag_state, info, kDagWaitLimitSeconds, D->dag_slots, st));
+  HIPCHK(launch_copy(info + 2, info, 2 * sizeof(unsigned long long), st));
+  *ran = true;
+  return GPR_OK;
+}
+
 int chol_impl(void* K, const TileLayout& L, int prec, void* ws, size_t ws_bytes, unsigned long long** info_out,
               hipStream_t st) {
   CholWs w = carve_chol(ws, L, prec, ws_bytes);
   if (info_out) *info_out = w.info + 2;   // set by the factorisation's last kernel
 
-  const bool la = g_lookahead.load(std::memory_order_relaxed) != 0;
+  const int mode = g_schedule.load(std::memory_order_relaxed);
+  if (mode == GPR_SCHEDULE_DEVICE && prec == GPR_FP64) {
+    bool ran = false;
+    int rc = chol_graph(K, L, prec, w, st, &ran);
+    if (rc || ran) return rc;
+  }
+  const bool la = mode != GPR_SCHEDULE_STREAM;
   if (!la)
     return run_program([&](Program& P) { describe_cholesky(P, L, K, prec, w, false); }, w.arena, w.arena_cap, st);
   // the auxiliary stream and events are shared by all calls on this device: serialise
@@ -924,7 +1169,13 @@ GPR_API int gpr_init(int64_t n, int64_t m, int64_t tile, int prec) {
 }
 
 GPR_API int gpr_set_lookahead(int on) {
-  g_lookahead.store(on != 0 ? 1 : 0, std::memory_order_relaxed);
+  g_schedule.store(on != 0 ? GPR_SCHEDULE_LOOKAHEAD : GPR_SCHEDULE_STREAM, std::memory_order_relaxed);
+  return GPR_OK;
+}
+
+GPR_API int gpr_set_schedule(int mode) {
+  if (mode < GPR_SCHEDULE_STREAM || mode > GPR_SCHEDULE_DEVICE) return fail(GPR_ERR_ARG, "unknown schedule %d", mode);
+  g_schedule.store(mode, std::memory_order_relaxed);
   return GPR_OK;
 }
 
@@ -989,6 +1240,10 @@ GPR_API int gpr_cholesky(void* K_tiles, int64_t n, int64_t tile, int prec, void*
     unsigned long long hinfo[1] = {0};
     HIPCHK(hipMemcpyAsync(hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (hinfo[0] == DAG_ABORT_INFO) {
+      *info = 0;
+      return fail(GPR_ERR_HIP, "device task graph gave up: a task waited longer than %.0f s", kDagWaitLimitSeconds);
+    }
     if (hinfo[0] != std::numeric_limits<unsigned long long>::max()) {
       *info = (int64_t)hinfo[0];
       return fail(GPR_ERR_NOT_SPD, "matrix is not positive definite: pivot %lld", (long long)hinfo[0]);
@@ -1360,6 +1615,114 @@ GPR_API int gpr_cholesky_schedule_check(int64_t n, int64_t tile, int prec, int64
   report[5] = r.conflicts;
   report[6] = r.unannotated;
   report[7] = r.early_waits;
+  return GPR_OK;
+}
+
+GPR_API int gpr_dag_check(int64_t n, int64_t tile, int threads, int64_t withhold, double limit_ms, int64_t* report) {
+  int rc;
+  if ((rc = check_shape(n, tile))) return rc;
+  if (!report || threads < 1 || threads > 4096 || !(limit_ms > 0)) return fail(GPR_ERR_ARG, "bad arguments");
+  for (int i = 0; i < 9; ++i) report[i] = 0;
+  if (n == 0) return GPR_OK;
+  const TileLayout L = layout_of(n, tile, GPR_FP64);
+  void* K = (void*)((uintptr_t)1 << 40);
+  const size_t wsb = chol_ws_bytes(L, GPR_FP64);
+  const CholWs w = carve_chol((void*)((uintptr_t)1 << 46), L, GPR_FP64, wsb);
+  Program P;
+  DagRecord R;
+  P.dagr = &R;
+  describe_cholesky_graph(P, L, K, GPR_FP64, w);
+  if (!R.ok) return fail(GPR_ERR_ARG, "this problem has no task-graph form");
+  std::vector<int32_t> succ;
+  if (!dag_edges(R, succ, dag_max_succ(R.tasks.size()))) return fail(GPR_ERR_ARG, "too many edges");
+  const int nt = (int)R.tasks.size();
+  if (withhold >= nt) return fail(GPR_ERR_ARG, "withhold >= number of tasks");
+  if (withhold <= -2) {
+    // drop edge number -2 - withhold (successor-list order) before the checks
+    const int64_t e = -2 - withhold;
+    if (e >= (int64_t)succ.size()) return fail(GPR_ERR_ARG, "no such edge");
+    int u = 0;
+    while (!(R.tasks[u].succ0 <= e && e < R.tasks[u].succ0 + R.tasks[u].nsucc)) ++u;
+    const int t = succ[e];
+    --R.tasks[t].npred;
+    for (int64_t q = e; q + 1 < R.tasks[u].succ0 + R.tasks[u].nsucc; ++q) succ[q] = succ[q + 1];
+    --R.tasks[u].nsucc;
+  }
+  std::vector<std::vector<int32_t>> preds(nt);
+  for (int u = 0; u < nt; ++u)
+    for (int q = 0; q < R.tasks[u].nsucc; ++q) preds[succ[R.tasks[u].succ0 + q]].push_back(u);
+  // Independent of how the edges were derived: every pair of tasks whose exact byte ranges
+  // overlap, one of them writing, must be ordered by a path of edges (graphs of up to 4096
+  // tasks; -1 above that).  Edges only run from earlier to later tasks.
+  int64_t unordered = -1;
+  if (nt <= 4096) {
+    unordered = 0;
+    const int words = (nt + 63) / 64;
+    std::vector<uint64_t> anc((size_t)nt * words, 0);
+    for (int t = 0; t < nt; ++t)
+      for (int32_t p : preds[t]) {
+        if (p >= t) ++unordered;   // an edge against the issue order
+        for (int q = 0; q < words; ++q) anc[(size_t)t * words + q] |= anc[(size_t)p * words + q];
+        anc[(size_t)t * words + p / 64] |= 1ull << (p % 64);
+      }
+    auto overlap = [](const std::vector<Span>& a, const std::vector<Span>& b) {
+      for (const Span& x : a)
+        for (const Span& y : b)
+          if (x.lo < y.hi && y.lo < x.hi) return true;
+      return false;
+    };
+    for (int t = 0; t < nt; ++t)
+      for (int u = 0; u < t; ++u) {
+        if (anc[(size_t)t * words + u / 64] >> (u % 64) & 1) continue;
+        if (overlap(R.wr[u], R.rd[t]) || overlap(R.wr[u], R.wr[t]) || overlap(R.rd[u], R.wr[t])) ++unordered;
+      }
+  }
+  std::vector<int32_t> state(dag_state_ints(nt), 0);
+  DagState S = dag_state_at(state.data(), nt);
+  for (int t = 0; t < nt; ++t) {
+    S.pending[t] = R.tasks[t].npred + (t == withhold ? 1 : 0);
+    S.remaining[t] = R.tasks[t].nitems;
+    S.rq0[t] = S.rq1[t] = -1;
+  }
+  std::vector<std::atomic<int64_t>> runs(R.items);   // how often each item ran (exactly once)
+  for (int t = 0; t < nt; ++t)
+    if (S.pending[t] == 0) HostCore::publish(R.tasks.data(), S, t);
+  std::atomic<int64_t> ran{0}, violations{0}, returned{0};
+  const uint64_t limit = (uint64_t)(limit_ms * 1.0e6);   // the host clock counts nanoseconds
+  std::atomic<int> next_lane{0};
+  auto worker = [&]() {
+    const int lane = next_lane.fetch_add(1) % DAG_LANES;
+    int last = -1;
+    uint64_t since = 0;
+    while (true) {
+      int t = 0, idx = 0, q = 0, h = 0;
+      if (!HostCore::try_claim(R.tasks.data(), S, lane, t, idx, q, h)) {
+        if (!HostCore::keep_waiting(S, last, since, limit)) break;
+        continue;
+      }
+      DagHostOps::fence_acquire();   // as the device executor before an item
+      runs[R.tasks[t].item0 + idx].fetch_add(1);
+      for (int32_t p : preds[t])
+        if (DagHostOps::load_acquire(&S.remaining[p]) != 0) violations.fetch_add(1);
+      ran.fetch_add(1);
+      HostCore::finish(R.tasks.data(), succ.data(), S, t);
+    }
+    returned.fetch_add(1);
+  };
+  std::vector<std::thread> pool;
+  for (int i = 0; i < threads; ++i) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+  report[0] = nt;
+  report[1] = R.items;
+  report[2] = (int64_t)succ.size();
+  report[3] = ran.load();
+  for (auto& r : runs)
+    if (r.load() != 1 && !S.ctl->abort) ++report[4];   // an item lost or run twice
+  report[4] = violations.load();
+  report[5] = S.ctl->abort;
+  report[6] = S.ctl->timed_out;
+  report[7] = returned.load();
+  report[8] = unordered;
   return GPR_OK;
 }
 

@@ -3,6 +3,7 @@
 #include <vector>
 
 #include "common.h"
+#include "dag.h"
 
 namespace gpr {
 
@@ -117,6 +118,15 @@ hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, in
 hipError_t launch_adam3(double* theta, double* state, const double* grad, double lr, double b1, double b2,
                         double eps, int t0, int t1, int t2, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
+
+// dag.hip: the persistent executor of a task graph (dag.h) on `st`, with `slots`
+// workgroups (dag_slots: as many as fit on the device at once) and its run state at
+// `state` (dag_state_ints(ntasks) int32); when no task finishes for limit_s seconds the run
+// gives up and DAG_ABORT_INFO is left in info[0].
+hipError_t dag_slots(int* slots);
+hipError_t launch_dag(const DagTask* tasks, int ntasks, const int32_t* succ, const DagOp* ops, const GemmJob* jobs,
+                      const GemmSeg* segs, int32_t* state, unsigned long long* info, double limit_s, int slots,
+                      hipStream_t st);
 
 // scratch.hip: file-scope device array of kScratchDoubles float64 (the partial sums of the
 // allocation-free prediction); scratch_setup() looks up its address on the current device

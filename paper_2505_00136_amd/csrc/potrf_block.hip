@@ -1,113 +1,17 @@
-// Factorisation and inversion of one diagonal block (up to 64 x 64) by one workgroup.
-//
-// The diagonal tile of each step of the tiled factorisation (the POTRF task of
-// Fig. 1) is factored by a blocked right-looking loop over 64-wide blocks (the
-// orchestration issues the block steps in stream order); this kernel handles the
-// diagonal block of each block step.  The block and its inverse live in registers:
-// 4 threads per row, thread t owns row t/4 and every fourth column starting at t%4, of
-// both A (becoming L) and W = L^{-1}.  Column j is eliminated with unscaled operands:
-// with a = column j of A and w = row j of W as they stand after step j-1,
-// l_ij l_kj = a_ij a_kj / a_jj and l_ij W_jc = a_ij w_c / a_jj, so each row i > j updates
-//   A_ik -= c a_kj  and  W_ic -= c w_c,   c = a_ij (1/L_jj)^2,
-// the right-looking Cholesky fused with forward elimination of L W = I.  Column k of A
-// and row i of W keep their unscaled values in registers until the final store applies
-// 1/L_kk and 1/L_ii.  One barrier per column: the threads that update column j+1 during
-// step j publish it (and the row of W that step j finishes, and the next pivot) into the
-// other half of double-buffered LDS exchange vectors, which are zero outside their ranges
-// (a_kj for k > j, w_c for c <= j), so the updates run unmasked over all of a thread's
-// columns (the entries they leave wrong, k > i, are never stored) and no register is
-// indexed at run time.
+// The workgroup kernel of one diagonal-block factorisation; the arithmetic is in
+// potrf_device.h.
 #include "common.h"
 #include "kernels.h"
+#include "potrf_device.h"
 
 namespace gpr {
 
-// Block edge PB, PB*4 threads; thread t owns row t/4 and columns t%4 + 4q.
 template <int PB>
 __global__ __launch_bounds__(PB * 4)
 void potrf_block_kernel(double* __restrict__ A, int64_t lda, double* __restrict__ W, int64_t ldw, int jb,
                         int64_t col_base, unsigned long long* info) {
-  constexpr int PQ = PB / 4;
-  // exchange vectors of step j in buffer j % 2, element k stored at [k % 4][k / 4] so
-  // that each thread's operands are contiguous: exl = column j of A (zero for k <= j),
-  // exw = row j of W (zero for c > j)
-  __shared__ __align__(16) double exl[2][4][PQ];
-  __shared__ __align__(16) double exw[2][4][PQ];
-  __shared__ double piv[PB];
-  __shared__ double ipiv[PB];
-  const int tid = threadIdx.x;
-  const int i = tid >> 2, cq = tid & 3;
-  double ra[PQ], rw[PQ];
-#pragma unroll
-  for (int q = 0; q < PQ; ++q) {
-    const int k = cq + 4 * q;
-    ra[q] = (i < jb && k <= i) ? A[(int64_t)i * lda + k] : 0.0;
-    rw[q] = (i < jb && k == i) ? 1.0 : 0.0;
-  }
-  // step 0's operands: column 0 of A below the diagonal, row 0 of W, the first pivot
-  if (cq == 0) exl[0][i & 3][i >> 2] = (i > 0 && i < jb) ? ra[0] : 0.0;
-  if (i == 0) {
-#pragma unroll
-    for (int q = 0; q < PQ; ++q) exw[0][cq][q] = rw[q];
-    if (cq == 0) {
-      const double d = ra[0];
-      if (!(d > 0.0)) atomicMin(info, (unsigned long long)(col_base + 1));
-      const double p = sqrt(d);
-      piv[0] = p;
-      ipiv[0] = 1.0 / p;
-    }
-  }
-  __syncthreads();
-  for (int j = 0; j < jb; ++j) {
-    const int cur = j & 1, nxt = cur ^ 1, j1 = j + 1;
-    const bool owner = cq == (j1 & 3);   // this thread holds column j+1 of its row
-    if (i > j && i < jb) {
-      const double inv = ipiv[j];
-      const double c = exl[cur][i & 3][i >> 2] * (inv * inv);
-      double el[PQ], ew[PQ];
-#pragma unroll
-      for (int q = 0; q < PQ; q += 2) {
-        const double2 vl = *reinterpret_cast<const double2*>(&exl[cur][cq][q]);
-        const double2 vw = *reinterpret_cast<const double2*>(&exw[cur][cq][q]);
-        el[q] = vl.x;
-        el[q + 1] = vl.y;
-        ew[q] = vw.x;
-        ew[q + 1] = vw.y;
-      }
-      double nv = 0.0;
-#pragma unroll
-      for (int q = 0; q < PQ; ++q) {
-        ra[q] = fma(-c, el[q], ra[q]);
-        rw[q] = fma(-c, ew[q], rw[q]);
-        nv = (cq + 4 * q == j1) ? ra[q] : nv;
-      }
-      if (owner) {
-        exl[nxt][i & 3][i >> 2] = i > j1 ? nv : 0.0;
-        if (i == j1) {
-          if (!(nv > 0.0)) atomicMin(info, (unsigned long long)(col_base + j1 + 1));
-          const double p = sqrt(nv);
-          piv[j1] = p;
-          ipiv[j1] = 1.0 / p;
-        }
-      }
-      if (i == j1) {                                        // row j+1 of W is final (unscaled)
-#pragma unroll
-        for (int q = 0; q < PQ; ++q) exw[nxt][cq][q] = rw[q];
-      }
-    } else if (owner) {
-      exl[nxt][i & 3][i >> 2] = 0.0;
-    }
-    __syncthreads();
-  }
-  // column k of A and row i of W kept their unscaled values in the registers
-#pragma unroll
-  for (int q = 0; q < PQ; ++q) {
-    const int k = cq + 4 * q;
-    if (i < jb && k < jb) {
-      A[(int64_t)i * lda + k] = k < i ? ra[q] * ipiv[k] : (k == i ? piv[k] : 0.0);
-      W[(int64_t)i * ldw + k] = k <= i ? rw[q] * ipiv[i] : 0.0;
-    }
-  }
+  __shared__ __align__(16) char smem[potrf_block_smem<PB>()];
+  potrf_block_work<PB, 4>(A, lda, W, ldw, jb, col_base, info, threadIdx.x, smem);
 }
 
 

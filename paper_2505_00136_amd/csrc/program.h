@@ -11,6 +11,7 @@
 #include <mutex>
 #include <vector>
 #include "common.h"
+#include "dag.h"
 #include "kernels.h"
 
 namespace gpr {
@@ -70,6 +71,26 @@ struct ScheduleReport {
 // omit_wait >= 0 analyses the schedule as if the waits on that event were missing.
 void check_schedule(const AccessLog& log, int omit_wait, ScheduleReport& rep);
 
+// A task graph recorded from a description (device-side schedule): one task per tile
+// product launch or other operation, in issue order, with the byte ranges it reads and
+// writes; the edges are derived from those ranges (dag_edges in abi.cpp).
+struct DagRecord {
+  std::vector<DagTask> tasks;
+  std::vector<DagOp> ops;
+  std::vector<std::vector<Span>> rd, wr;
+  int32_t items = 0;
+  int32_t prio = 1;   // ready queue of the tasks recorded next
+  bool ok = true;   // false when an operation has no task form (the caller falls back to streams)
+  void add(DagTask t, std::vector<Span> r, std::vector<Span> w) {
+    t.item0 = items;
+    t.prio = prio;
+    items += t.nitems;
+    tasks.push_back(t);
+    rd.push_back(std::move(r));
+    wr.push_back(std::move(w));
+  }
+};
+
 struct Program {
   bool exec = false;
   hipStream_t st = nullptr;        // the caller's stream
@@ -93,6 +114,7 @@ struct Program {
   const TraceArgs* trace = nullptr;
   int64_t trace_wg = 0, trace_cap = 0;
   AccessLog* alog = nullptr;   // trace pass: log accesses, launch nothing
+  DagRecord* dagr = nullptr;   // task-graph pass: record tasks, launch nothing
 
   hipStream_t stream() const { return cur == 1 && aux ? aux : st; }
   void on(int s) { cur = s; }
@@ -168,6 +190,24 @@ struct Program {
   void gemm_end() {
     const int nj = (int)jobs.size() - job0;
     if (alog && nj > 0) log_gemm(nj);
+    if (dagr) {
+      if (nj == 0) return;
+      if (f32 || kind == GEMM_KIND_TRACE || gemm_kind_macro(kind) != GEMM_BM || kind == GEMM_KIND_WIDEN ||
+          gemm_kind_bf16(kind)) {
+        dagr->ok = false;   // the task form covers the float64 tile products only
+        return;
+      }
+      DagTask t{};
+      t.kind = DAG_GEMM;
+      t.spec = gemm_launch_spec(jobs.data() + job0, nj, segs.data(), 8, 16);
+      t.nitems = nwg;
+      t.job0 = job0;
+      t.njobs = nj;
+      std::vector<Span> rd, wr;
+      gemm_spans(nj, rd, wr);
+      dagr->add(t, std::move(rd), std::move(wr));
+      return;
+    }
     if (!exec || err != hipSuccess || nj == 0) return;
     gemm_flops_wg += nwg;
     hipEvent_t ea = nullptr, eb = nullptr;
@@ -228,6 +268,10 @@ struct Program {
   // `rd` / `wr`: the byte ranges the launch reads / writes (read-modify-write counts as a
   // write), for the trace pass.
   void kernel(const std::function<hipError_t(hipStream_t)>& fn) {
+    if (dagr) {
+      dagr->ok = false;
+      return;
+    }
     if (alog) {
       alog->ops.push_back({AccessLog::LAUNCH, cur, -1, {}, {}});
       alog->unannotated++;
@@ -236,15 +280,44 @@ struct Program {
     err = fn(stream());
   }
   void kernel(const std::function<hipError_t(hipStream_t)>& fn, std::vector<Span> rd, std::vector<Span> wr) {
+    if (dagr) {
+      dagr->ok = false;
+      return;
+    }
     if (alog) alog->ops.push_back({AccessLog::LAUNCH, cur, -1, std::move(rd), std::move(wr)});
     if (!exec || err != hipSuccess) return;
     err = fn(stream());
+  }
+
+  // An operation other than a tile product: launched by `fn` (streams), or recorded as a
+  // task of `nitems` items described by `d` (task-graph pass).
+  void op(int dag_kind, const DagOp& d, int64_t nitems, const std::function<hipError_t(hipStream_t)>& fn,
+          std::vector<Span> rd, std::vector<Span> wr) {
+    if (dagr) {
+      if (nitems <= 0) return;
+      DagTask t{};
+      t.kind = dag_kind;
+      t.nitems = (int32_t)nitems;
+      t.op = (int32_t)dagr->ops.size();
+      dagr->ops.push_back(d);
+      dagr->add(t, std::move(rd), std::move(wr));
+      return;
+    }
+    kernel(fn, std::move(rd), std::move(wr));
   }
 
   // Access ranges of the open tile-GEMM launch: C (and Cin) of every job, the operand
   // extents of its segments (all planes in the split modes).
   void log_gemm(int nj) {
     AccessLog::Op op{AccessLog::LAUNCH, cur, -1, {}, {}};
+    gemm_spans(nj, op.rd, op.wr);
+    alog->ops.push_back(std::move(op));
+  }
+  void gemm_spans(int nj, std::vector<Span>& rd, std::vector<Span>& wr) const {
+    struct {
+      std::vector<Span>& rd;
+      std::vector<Span>& wr;
+    } op{rd, wr};
     const bool split = gemm_kind_bf16(kind);
     const int oe = split ? 2 : ((f32 || kind == GEMM_KIND_WIDEN) ? 4 : 8);
     const int planes = split ? (gemm_kind_nprod(kind) == 6 ? 3 : 2) : 1;
@@ -263,7 +336,6 @@ struct Program {
         }
       }
     }
-    alog->ops.push_back(std::move(op));
   }
 };
 
