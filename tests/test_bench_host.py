@@ -34,8 +34,8 @@ def test_traffic_record_tracks_the_kernel_source(tmp_path, monkeypatch):
     assert rec["bytes_per_launch"][kernel] > 0
     src = tmp_path / "gemm.hip"
     src.write_text("// another kernel source\n")
-    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
     assert bench.recorded_traffic(kernel) is None
-    monkeypatch.setattr(bench, "KERNEL_SOURCE", os.path.join(ROOT, rec["kernel_source"]))
-    if bench.source_digest(bench.KERNEL_SOURCE) == rec["kernel_source_sha256_16"]:
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [os.path.join(ROOT, f) for f in rec["kernel_sources"]])
+    if bench.source_digest(bench.KERNEL_SOURCES) == rec["kernel_source_sha256_16"]:
         assert bench.recorded_traffic(kernel) == rec["bytes_per_launch"][kernel]

@@ -145,6 +145,19 @@ def test_lookahead_matches_single_stream_bitwise(full):
         assert torch.equal(a1, a0) and n1 == n0
 
 
+def test_device_schedule_matches_lookahead_bitwise(full):
+    """The task graph executed on the device gives the factor and alpha of the stream
+    schedules, bit for bit, at the full size (3693 tasks, 2.4 million work items)."""
+    lib = full["lib"]
+    a0, n0 = full["fit"](H)
+    lib.gpr_set_schedule("device")
+    try:
+        a1, n1 = full["fit"](H)
+    finally:
+        lib.gpr_set_schedule("lookahead")
+    assert torch.equal(a1, a0) and n1 == n0
+
+
 def test_gradient_against_central_differences(full):
     lib = full["lib"]
     grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
