@@ -1,6 +1,8 @@
 """GPU parity at n = 16384 training points, D = 8, 4096 test points, tile 1024 (16 x 16
 tiles), the float64 configuration with full predictive covariance, NLML, gradient and
-10 Adam steps (lr 0.1) from theta = (0, 0, log 0.1).
+10 Adam steps (lr 0.1) from theta = (0, 0, log 0.1).  The same problem with a single
+16384 x 16384 tile (T = 1, the paper's sequential baseline of Section 5.2, whose
+factorisation is the in-tile blocked loop alone) is checked against the same oracle.
 
 At this size the oracle still runs completely on the host (a 16384^2 Cholesky, a
 16384 x 4096 triangular solve, the explicit inverse for the gradient: tens of seconds),
@@ -78,6 +80,38 @@ def run():
     return got, ref
 
 
+@pytest.fixture(scope="module")
+def single_tile(run):
+    """alpha, NLML, mean, variance and gradient with one tile of 16384 rows."""
+    from paper_2505_00136_amd import _lib
+    _, ref = run
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=N, n_test=M, D=D, seed=SEED))
+    dev = torch.device("cuda:0")
+    Z, Zs, y = (torch.tensor(a, device=dev) for a in (ds.Z, ds.Zs, ds.y))
+    h = (H.lengthscale, H.signal_var, H.noise_var)
+    print("[n16384] single tile", flush=True)
+    wsb = _lib.gpr_workspace_size(N, M, D, N, "fp64")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    K = torch.empty(_lib.gpr_tiles_bytes(N, N, "fp64"), dtype=torch.uint8, device=dev)
+    alpha = torch.empty(N, dtype=torch.float64, device=dev)
+    nl = torch.empty(1, dtype=torch.float64, device=dev)
+    mean = torch.empty(M, dtype=torch.float64, device=dev)
+    var = torch.empty(M, dtype=torch.float64, device=dev)
+    grad = torch.empty(3, dtype=torch.float64, device=dev)
+    _lib.gpr_assemble(Z, N, D, h, N, "fp64", K)
+    assert _lib.gpr_cholesky(K, N, N, "fp64", ws, wsb) == 0
+    _lib.gpr_solve(K, Z, N, D, h, N, "fp64", y, alpha, 0, ws, wsb)
+    _lib.gpr_nlml(K, N, N, "fp64", y, alpha, nl)
+    _lib.gpr_predict(Z, N, Zs, M, D, h, alpha, mean, ws, wsb)
+    _lib.gpr_predict_var(Z, N, Zs, M, D, h, K, N, "fp64", False, False, var, ws, wsb)
+    _lib.gpr_nlml_grad(Z, N, D, h, K, N, "fp64", alpha, (1, 1, 1), grad, ws, wsb)
+    torch.cuda.synchronize()
+    got = dict(alpha=alpha.cpu().numpy(), nlml=float(nl.item()), mean=mean.cpu().numpy(), var=var.cpu().numpy(),
+               grad=grad.cpu().numpy())
+    del ws, K
+    return got, ref
+
+
 def test_alpha_nlml_mean(run):
     got, ref = run
     assert_close(got["alpha"], ref["alpha"], 1e-10, what="alpha")
@@ -108,3 +142,12 @@ def test_adam_steps(run):
     th1 = np.array(THETA0) - 0.1 * g / (np.abs(g) + 1e-8)
     np.testing.assert_allclose(got["theta1"], th1, rtol=1e-12, atol=1e-12)
     assert np.all(np.isfinite(got["theta"]))
+
+
+def test_single_tile(single_tile):
+    got, ref = single_tile
+    assert_close(got["alpha"], ref["alpha"], 1e-10, what="alpha (one tile)")
+    assert abs(got["nlml"] - ref["nlml"]) / abs(ref["nlml"]) < 1e-10
+    assert_close(got["mean"], ref["mean"], 1e-10, what="mean (one tile)")
+    assert_close(got["var"], ref["var"], 1e-10, what="variance (one tile)")
+    np.testing.assert_allclose(got["grad"], ref["grad"], rtol=1e-9, atol=1e-9 * np.max(np.abs(ref["grad"])))
