@@ -45,8 +45,14 @@ WORKLOADS = {
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gemm_kernel_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_00136_amd", "csrc", f)
-                  for f in ("gemm.hip", "gemm_device.h", "gemm_bf16.hip")]
+# the sources of each tile-product kernel family; a traffic figure is reported only while
+# its family's sources are the ones it was measured with
+KERNEL_SOURCES = {"f64_f32": [os.path.join(ROOT, "paper_2505_00136_amd", "csrc", f) for f in ("gemm.hip", "gemm_device.h")],
+                  "bf16": [os.path.join(ROOT, "paper_2505_00136_amd", "csrc", "gemm_bf16.hip")]}
+
+
+def kernel_family(kernel: str) -> str:
+    return "bf16" if "bf16" in kernel else "f64_f32"
 # timing kinds of the library's event hook -> kernel symbol, operand dtype.  The symbols are
 # the operand-mode specialisations that run for this workload's whole 2048-wide tiles
 # (update and trace: MC/MC = 3; the inversion's row-scaling launches are KC/MC = 1 and its
@@ -79,13 +85,14 @@ def source_digest(paths) -> str:
 
 def recorded_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter record, or None when the
-    record is missing, does not cover the kernel, or the kernel source changed since."""
+    record is missing, does not cover the kernel, or the kernel's sources changed since."""
     try:
         with open(TRAFFIC_RECORD) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256_16") != source_digest(KERNEL_SOURCES):
+    fam = kernel_family(kernel)
+    if rec.get("source_families", {}).get(fam, {}).get("sha256_16") != source_digest(KERNEL_SOURCES[fam]):
         return None
     return rec.get("bytes_per_launch", {}).get(kernel)
 

@@ -66,6 +66,8 @@ constexpr int DAG_LANES = 8;
 
 // Device state of one graph run: per task the unfinished predecessors, the unfinished
 // items, the next item of each lane, and the two ready queues (-1: slot not written yet).
+// The lane counters are stored lane by lane, so that the workgroups of different XCDs
+// claiming items of one task increment counters in different cache lines.
 struct DagState {
   int32_t *pending, *remaining, *next_item, *rq0, *rq1;
   DagCtl* ctl;
@@ -78,7 +80,7 @@ GPR_HD inline DagState dag_state_at(int32_t* base, int32_t ntasks) {
   S.remaining = base + ntasks;
   S.rq0 = base + 2 * (size_t)ntasks;
   S.rq1 = base + 3 * (size_t)ntasks;
-  S.next_item = base + 4 * (size_t)ntasks;   // [task][lane]
+  S.next_item = base + 4 * (size_t)ntasks;   // [lane][task]: each lane's counters in lines of their own
   S.ctl = (DagCtl*)(base + (((4 + DAG_LANES) * (size_t)ntasks + 15) & ~(size_t)15));
   S.ntasks = ntasks;
   return S;
@@ -123,7 +125,7 @@ struct DagCore {
           const int lane = (x + c) % DAG_LANES;
           const int lo = (int)((int64_t)n * lane / DAG_LANES), hi = (int)((int64_t)n * (lane + 1) / DAG_LANES);
           if (lo >= hi) continue;
-          const int i = Ops::fetch_add_relaxed(&S.next_item[(size_t)tt * DAG_LANES + lane], 1);
+          const int i = Ops::fetch_add_relaxed(&S.next_item[(size_t)lane * S.ntasks + tt], 1);
           if (lo + i < hi) {
             t = tt;
             idx = lo + i;

@@ -66,7 +66,7 @@ __global__ void dag_reset_kernel(DagArgs a) {
   if (i < a.ntasks) {
     S.pending[i] = a.tasks[i].npred;
     S.remaining[i] = a.tasks[i].nitems;
-    for (int l = 0; l < DAG_LANES; ++l) S.next_item[(size_t)i * DAG_LANES + l] = 0;
+    for (int l = 0; l < DAG_LANES; ++l) S.next_item[(size_t)l * a.ntasks + i] = 0;
     S.rq0[i] = -1;
     S.rq1[i] = -1;
   }

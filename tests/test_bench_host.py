@@ -32,10 +32,12 @@ def test_traffic_record_tracks_the_kernel_source(tmp_path, monkeypatch):
         rec = json.load(f)
     kernel = "gemm_trace_kernel<double, 3>"
     assert rec["bytes_per_launch"][kernel] > 0
+    assert bench.kernel_family(kernel) == "f64_f32" and bench.kernel_family("gemm_bf16x_t256_kernel<6>") == "bf16"
     src = tmp_path / "gemm.hip"
     src.write_text("// another kernel source\n")
-    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", {"f64_f32": [str(src)], "bf16": [str(src)]})
     assert bench.recorded_traffic(kernel) is None
-    monkeypatch.setattr(bench, "KERNEL_SOURCES", [os.path.join(ROOT, f) for f in rec["kernel_sources"]])
-    if bench.source_digest(bench.KERNEL_SOURCES) == rec["kernel_source_sha256_16"]:
+    fam = rec["source_families"]["f64_f32"]
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", {"f64_f32": [os.path.join(ROOT, f) for f in fam["files"]], "bf16": []})
+    if bench.source_digest(bench.KERNEL_SOURCES["f64_f32"]) == fam["sha256_16"]:
         assert bench.recorded_traffic(kernel) == rec["bytes_per_launch"][kernel]

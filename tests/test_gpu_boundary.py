@@ -74,25 +74,27 @@ def test_calls_return_while_the_stream_is_busy(lib):
     assert torch.equal(var, ref[1]) and torch.equal(grad, ref[2])
 
 
-def test_lookahead_switch(lib):
-    """gpr_set_lookahead(0) and (1) give the same bits."""
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3"])
+def test_lookahead_switch(lib, prec):
+    """gpr_set_lookahead(0) and (1) give the same bits, in every precision, and repeated
+    look-ahead factorisations agree."""
     n, tile, d = 1536, 256, 5
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=n, n_test=4, D=d, seed=42))
     dev = "cuda:0"
     Z = torch.tensor(ds.Z, device=dev)
-    wsb = lib.gpr_workspace_size(n, 0, d, tile, "fp64")
+    wsb = lib.gpr_workspace_size(n, 0, d, tile, prec)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     out = []
-    for la in (False, True):
-        K = torch.empty(lib.gpr_tiles_bytes(n, tile, "fp64"), dtype=torch.uint8, device=dev)
+    for la in (False, True, True):
+        K = torch.empty(lib.gpr_tiles_bytes(n, tile, prec), dtype=torch.uint8, device=dev)
         lib.gpr_set_lookahead(la)
         try:
-            lib.gpr_assemble(Z, n, d, (1.1, 0.9, 0.03), tile, "fp64", K)
-            assert lib.gpr_cholesky(K, n, tile, "fp64", ws, wsb) == 0
+            lib.gpr_assemble(Z, n, d, (1.1, 0.9, 0.03), tile, prec, K)
+            assert lib.gpr_cholesky(K, n, tile, prec, ws, wsb) == 0
         finally:
             lib.gpr_set_lookahead(True)
         out.append(K)
-    assert torch.equal(out[0], out[1])
+    assert torch.equal(out[0], out[1]) and torch.equal(out[1], out[2])
 
 
 def test_autograd_two_forwards_then_two_backwards(lib):
