@@ -135,8 +135,15 @@ def cholesky(K: np.ndarray) -> np.ndarray:
 
 
 def potrf_info(K: np.ndarray) -> int:
-    """LAPACK convention: 0 if K is positive definite, else the 1-based column of the first bad pivot."""
-    _, info = lapack.dpotrf(np.array(K, dtype=np.float64, order="F"), lower=1, clean=1)
+    """LAPACK convention: 0 if K is positive definite, else the 1-based column of the first
+    bad pivot -- non-positive or NaN.  Some BLAS builds of dpotrf test only for <= 0; a NaN
+    pivot then leaves a NaN diagonal entry of the factor (the earlier ones are finite, the
+    later ones NaN too), so the first NaN on the diagonal names that column."""
+    L, info = lapack.dpotrf(np.array(K, dtype=np.float64, order="F"), lower=1, clean=1)
+    if info == 0:
+        bad = np.flatnonzero(np.isnan(np.diag(L)))
+        if bad.size:
+            return int(bad[0]) + 1
     return int(info)
 
 

@@ -75,7 +75,7 @@ def _textbook_cholesky(A):
     L = [[0.0] * n for _ in range(n)]
     for j in range(n):
         s = A[j][j] - sum(L[j][k] ** 2 for k in range(j))
-        if s <= 0:
+        if not s > 0:   # a non-positive or NaN pivot
             return None, j + 1
         L[j][j] = math.sqrt(s)
         for i in range(j + 1, n):
@@ -107,6 +107,18 @@ def test_potrf_info_matches_textbook_first_bad_pivot():
         assert info_tb == col
         assert oracle.potrf_info(Kb) == col
     assert oracle.potrf_info(K) == 0
+
+
+def test_potrf_info_nan_input_is_its_column():
+    """A NaN training input makes its row and column of K NaN: the pivots before it stay
+    finite and its own pivot fails the positivity test, as in the textbook loop."""
+    for row in (0, 3, 8):
+        Z = _rand_pts(9, 2, 4)
+        Z[row, 0] = float("nan")
+        K = oracle.train_cov(Z, Hyper(1.0, 1.0, 0.1))
+        _, info_tb = _textbook_cholesky(K.tolist())
+        assert info_tb == row + 1
+        assert oracle.potrf_info(K) == row + 1
 
 
 # ---------------------------------------------------------------- P4, P5: log-det and alpha
