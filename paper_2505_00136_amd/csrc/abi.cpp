@@ -94,7 +94,14 @@ TileLayout layout_of(int64_t n, int64_t tile, int prec) {
   return L;
 }
 
-// Sequential carving of a workspace into 256-byte aligned regions.
+// Symbolic addresses for the passes that only size or analyse a description (no memory
+// behind them): the tiled matrix, the workspace and an output, far apart.
+void* const kSymK = (void*)((uintptr_t)1 << 40);
+void* const kSymOut = (void*)((uintptr_t)1 << 43);
+void* const kSymWs = (void*)((uintptr_t)1 << 46);
+
+// Sequential carving of a workspace into 256-byte aligned regions.  With a null base it
+// only sizes (the regions are then null too: no arithmetic on a null pointer).
 struct Carve {
   char* base;
   size_t off = 0;
@@ -102,7 +109,7 @@ struct Carve {
   template <typename T>
   T* take(size_t count) {
     off = (off + 255) & ~(size_t)255;
-    T* p = (T*)(base + off);
+    T* p = base ? (T*)(base + off) : nullptr;
     off += count * sizeof(T);
     return p;
   }
@@ -283,7 +290,7 @@ struct CholWs {
   void* panel;      // copy of the panel below the diagonal tile (TRSM source)
   float* w32;       // float32 copy of the diagonal-tile inverse (mixed)
   uint16_t* planes; // hi/mid/lo bfloat16 planes of the solved panel (split modes), stride (T-1) b^2, two sets
-  void* panel_t;    // transposed tiles of the solved panel (other modes), (T-1) b^2 elements, two sets
+  void* panel_t;    // transposed tiles of the solved panel, (T-1) b^2 elements, two sets
   int32_t* dag_state;   // task-graph schedule (float64): per-task counters and the control words
   int64_t dag_ntasks;
 
@@ -363,16 +370,17 @@ double add_trsm_job(Program& P, const TileLayout& L, void* K, int prec, const Ch
   return (double)(T - k - 1) * bd * bd * (bd + 1.0);
 }
 
-// Transposed copies of the solved panel k's tiles (float64 and float32 modes), buffer set
-// k mod 2: the trailing update reads both of its operands m-contiguous, the operand order
-// its main loop stages fastest (measured 4-5% over k-contiguous operands).
+// Transposed copies of the solved panel k's tiles, buffer set k mod 2: the trailing update
+// (float64, float32) and the mixed modes' diagonal-tile SYRK read both of their operands
+// m-contiguous, the operand order the main loop stages fastest (measured 4-5% over
+// k-contiguous operands on the float64 update).
 void* panel_t_set(const TileLayout& L, const CholWs& w, int64_t k) {
   return (char*)w.panel_t + (size_t)(k & 1) * (L.T - 1) * L.b * L.b * L.esize;
 }
 
 void describe_transpose(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k) {
   const int64_t b = L.b, T = L.T;
-  if (is_bf16(prec) || k >= T - 1) return;
+  if (k >= T - 1) return;
   const void* panel = L.off(K, k + 1, k);
   void* dst = panel_t_set(L, w, k);
   const int64_t count = T - k - 1;
@@ -429,11 +437,15 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
     gemm_flops += 2.0 * (double)(T - nn - 1) * bd * bd * bd;
   }
   if (mixed) {
+    // the SYRK into the float64 diagonal tiles, float64 products of the float32 panel,
+    // both operands m-contiguous from the transposed panel tiles
+    const char* ptk = (const char*)panel_t_set(L, w, k);
     P.gemm_begin(0, GEMM_KIND_WIDEN);
     for (int64_t m = n0; m < n1; ++m) {
       double* Cm = L.diag(K, m);
+      const void* Tm = ptk + (size_t)(m - k - 1) * b * b * L.esize;
       P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
-      P.seg(L.off(K, m, k), b, MODE_KC, L.off(K, m, k), b, MODE_KC, b, 0);
+      P.seg(Tm, b, MODE_MC, Tm, b, MODE_MC, b, 0);
     }
     P.gemm_end();
   }
@@ -641,6 +653,8 @@ size_t dag_table_bytes(const Program& P, const DagRecord& R) {
 }
 
 // Number of tasks of the float64 graph of a layout (recorded once per (n, b), then cached).
+CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes, bool with_dag = true);
+
 int64_t dag_task_count(const TileLayout& L) {
   static std::mutex mu;
   static std::map<std::pair<int64_t, int64_t>, int64_t> cache;
@@ -650,8 +664,8 @@ int64_t dag_task_count(const TileLayout& L) {
   Program P;
   DagRecord R;
   P.dagr = &R;
-  CholWs w{};
-  describe_cholesky_graph(P, L, nullptr, GPR_FP64, w);
+  const CholWs w = carve_chol(kSymWs, L, GPR_FP64, 0, false);
+  describe_cholesky_graph(P, L, kSymK, GPR_FP64, w);
   const int64_t nt = (int64_t)R.tasks.size();
   cache[{L.n, L.b}] = nt;
   return nt;
@@ -667,33 +681,33 @@ CholSizes chol_sizes(const TileLayout& L, int prec) {
   c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   if (is_mixed(prec)) c.take<float>((size_t)L.b * L.b);
   if (is_bf16(prec)) c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b);
-  else c.take<char>((size_t)2 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
+  c.take<char>((size_t)2 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   Program P1, P2;
-  CholWs w{};
-  describe_cholesky(P1, L, nullptr, prec, w, false);
-  describe_cholesky(P2, L, nullptr, prec, w, true);
+  const CholWs w = carve_chol(kSymWs, L, prec, 0, false);
+  describe_cholesky(P1, L, kSymK, prec, w, false);
+  describe_cholesky(P2, L, kSymK, prec, w, true);
   size_t arena = std::max(arena_bytes_of(P1), arena_bytes_of(P2));
   if (prec == GPR_FP64) {
     // the task graph's tables and its per-task counters
     Program P3;
     DagRecord R;
     P3.dagr = &R;
-    describe_cholesky_graph(P3, L, nullptr, prec, w);
+    describe_cholesky_graph(P3, L, kSymK, prec, w);
     arena = std::max(arena, dag_table_bytes(P3, R));
     c.take<int32_t>(dag_state_ints(dag_task_count(L)));
   }
   return CholSizes{c.off, arena};
 }
 
-CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes) {
+CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes, bool with_dag) {
   Carve c(ws);
   CholWs w{};
   w.info = c.take<unsigned long long>(32);
   w.panel = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.b * L.b) : nullptr;
   w.planes = is_bf16(prec) ? c.take<uint16_t>((size_t)6 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b) : nullptr;
-  w.panel_t = is_bf16(prec) ? nullptr : c.take<char>((size_t)2 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
-  if (prec == GPR_FP64) {
+  w.panel_t = c.take<char>((size_t)2 * (L.T > 1 ? L.T - 1 : 0) * L.b * L.b * L.esize);
+  if (prec == GPR_FP64 && with_dag) {
     w.dag_ntasks = dag_task_count(L);
     w.dag_state = c.take<int32_t>(dag_state_ints(w.dag_ntasks));
   }
@@ -993,20 +1007,20 @@ int grad_impl(const double* Z, int64_t d, HyperArg h, void* K, const TileLayout&
 }
 
 size_t grad_ws_bytes(const TileLayout& L, int prec) {
-  Carve c(nullptr);
+  Carve c(kSymWs);
   GradWs w = carve_grad(c, L, prec);
   Program P1, P2;
-  describe_trtri(P1, L, nullptr, prec, w);
-  describe_lauum_trace(P2, L, nullptr, prec, w);
+  describe_trtri(P1, L, kSymK, prec, w);
+  describe_lauum_trace(P2, L, kSymK, prec, w);
   return c.off + std::max(arena_bytes_of(P1), arena_bytes_of(P2));
 }
 
 size_t var_ws_bytes(const TileLayout& L, int64_t m, int prec, bool full) {
-  Carve c(nullptr);
+  Carve c(kSymWs);
   VarWs w = carve_var(c, L, m, prec);
   Program P;
-  describe_var(P, L, nullptr, m, prec, w);
-  if (full) describe_fullcov(P, L, m, prec, w, nullptr);
+  describe_var(P, L, kSymK, m, prec, w);
+  if (full) describe_fullcov(P, L, m, prec, w, (double*)kSymOut);
   return c.off + arena_bytes_of(P);
 }
 
@@ -1055,19 +1069,19 @@ typedef DagCore<DagHostOps> HostCore;
 size_t table_bytes(const TileLayout& L, int64_t m, int prec) {
   size_t t = chol_sizes(L, prec).arena;
   {
-    Carve c(nullptr);
+    Carve c(kSymWs);
     VarWs w = carve_var(c, L, m, prec);
     Program P;
-    describe_var(P, L, nullptr, m, prec, w);
-    describe_fullcov(P, L, m, prec, w, nullptr);
+    describe_var(P, L, kSymK, m, prec, w);
+    describe_fullcov(P, L, m, prec, w, (double*)kSymOut);
     t = std::max(t, arena_bytes_of(P));
   }
   {
-    Carve c(nullptr);
+    Carve c(kSymWs);
     GradWs w = carve_grad(c, L, prec);
     Program P1, P2;
-    describe_trtri(P1, L, nullptr, prec, w);
-    describe_lauum_trace(P2, L, nullptr, prec, w);
+    describe_trtri(P1, L, kSymK, prec, w);
+    describe_lauum_trace(P2, L, kSymK, prec, w);
     t = std::max(t, std::max(arena_bytes_of(P1), arena_bytes_of(P2)));
   }
   return t;
@@ -1598,9 +1612,9 @@ GPR_API int gpr_cholesky_schedule_check(int64_t n, int64_t tile, int prec, int64
   }
   // symbolic addresses: the trace pass only compares them, nothing is dereferenced
   const TileLayout L = layout_of(n, tile, prec);
-  void* K = (void*)((uintptr_t)1 << 40);
+  void* K = kSymK;
   const size_t wsb = chol_ws_bytes(L, prec);
-  const CholWs w = carve_chol((void*)((uintptr_t)1 << 46), L, prec, wsb);
+  const CholWs w = carve_chol(kSymWs, L, prec, wsb);
   AccessLog log;
   Program P;
   P.alog = &log;
@@ -1625,9 +1639,9 @@ GPR_API int gpr_dag_check(int64_t n, int64_t tile, int threads, int64_t withhold
   for (int i = 0; i < 9; ++i) report[i] = 0;
   if (n == 0) return GPR_OK;
   const TileLayout L = layout_of(n, tile, GPR_FP64);
-  void* K = (void*)((uintptr_t)1 << 40);
+  void* K = kSymK;
   const size_t wsb = chol_ws_bytes(L, GPR_FP64);
-  const CholWs w = carve_chol((void*)((uintptr_t)1 << 46), L, GPR_FP64, wsb);
+  const CholWs w = carve_chol(kSymWs, L, GPR_FP64, wsb);
   Program P;
   DagRecord R;
   P.dagr = &R;

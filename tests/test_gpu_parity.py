@@ -215,6 +215,25 @@ def test_not_spd_reports_first_bad_column(lib):
         assert lib.gpr_cholesky(K, n, tile, "fp64", ws, wsb) == oracle.potrf_info(Kh) == col
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
+def test_nan_input_reports_its_column(lib, prec):
+    """A NaN in one training input makes its row and column of K NaN; every pivot before it
+    stays finite, so the factorisation reports that column as the first bad pivot (1-based),
+    as LAPACK's dpotrf does on the oracle's matrix (a NaN pivot fails the positivity test)."""
+    rng = np.random.default_rng(5)
+    n, tile, D = 512, 128, 3
+    h = Hyper(1.0, 1.0, 0.1)
+    dev = "cuda:0"
+    for row in (0, 130, 511):
+        Z = rng.normal(size=(n, D))
+        Z[row, 1] = np.nan
+        K = torch.empty(lib.gpr_tiles_bytes(n, tile, prec), dtype=torch.uint8, device=dev)
+        wsb = lib.gpr_workspace_size(n, 0, D, tile, prec)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        lib.gpr_assemble(torch.tensor(Z, device=dev), n, D, h, tile, prec, K)
+        assert lib.gpr_cholesky(K, n, tile, prec, ws, wsb) == oracle.potrf_info(oracle.train_cov(Z, h)) == row + 1
+
+
 def test_gradient_parity(lib):
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=512, n_test=8, D=8, seed=2))
     h = Hyper(1.3, 0.8, 0.05)
