@@ -407,7 +407,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path is a design "
+        print(json.dumps({"error": "this library runs on one GPU only; the multi-GPU path is a design "
                                    "(tile-cyclic sharding) and is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     run(args)

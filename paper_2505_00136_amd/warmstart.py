@@ -5,7 +5,7 @@ dataset to initial log-hyperparameters theta = log(l, nu, sigma^2) for the Adam
 optimisation of Section 4.1.  Everything numeric runs in the library's kernels:
 the statistics (gpr_summary_stats), the network (gpr_mlp_forward /
 gpr_mlp_train_step) and the labels and evaluations (gpr_optimize).  The default
-initialisation theta = (0, 0, log 0.1) stays the fallback and the judge: the learned
+initialisation theta = (0, 0, log 0.1) stays the fallback and the yardstick: the learned
 initialisation is used only when its NLML is lower.
 
 Workload: mass-spring-damper datasets with m ~ U[0.5, 2], c ~ U[0.1, 1], k ~ U[0.5, 2],
