@@ -123,7 +123,9 @@ GPR_API int gpr_init(int64_t n, int64_t m, int64_t tile, int prec);
  *  GPR_SCHEDULE_STREAM:    every launch on the caller's stream, in the order of Fig. 1.
  *  GPR_SCHEDULE_LOOKAHEAD: (the default) diagonal tile k+1 and its panel are factored on an
  *                          auxiliary stream while step k's remaining update runs on the
- *                          caller's stream, events ordering the two.
+ *                          caller's stream, events ordering the two (in the mixed
+ *                          precisions the diagonal tile starts as soon as step k has updated
+ *                          it, beside the update of the rest of its block column).
  *  GPR_SCHEDULE_DEVICE:    the tasks of Fig. 1 (and the block steps inside the diagonal
  *                          tiles) form a graph whose edges are their tile dependencies
  *                          (Section 4.2's dataflow), executed by one persistent kernel: a
@@ -352,7 +354,8 @@ GPR_API int gpr_cholesky_census(int64_t T, int64_t* counts);
  * touch common bytes with at least one writing (a correct schedule has none), launches
  * without access ranges, waits issued before their event was recorded.  omit_event >= 0
  * analyses the schedule as if every wait on that event were missing (event 0: start,
- * 1 + 2k: column k+1 of step k updated, 2 + 2k: panel k solved); -1 analyses it as issued.
+ * 1 + 3k: diagonal tile k+1 updated by step k, 2 + 3k: the rest of block column k+1
+ * updated by step k, 3 + 3k: panel k solved); -1 analyses it as issued.
  * Touches no device memory.  Errors: GPR_ERR_ARG (unknown precision tag or NULL report),
  * GPR_ERR_SHAPE. */
 GPR_API int gpr_cholesky_schedule_check(int64_t n, int64_t tile, int prec, int64_t omit_event, int64_t* report);

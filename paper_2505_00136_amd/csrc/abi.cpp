@@ -418,8 +418,12 @@ void describe_split(Program& P, const TileLayout& L, void* K, int prec, const Ch
 // GEMM elsewhere).  Mixed modes: the SYRK on the float64 diagonal tiles multiplies the
 // float32 panel in float64 (exact products, so the pivots do not inherit float32
 // accumulation error); the GEMM tiles use the mode's products.
+// Which tiles of the block columns an update covers: the diagonal tiles (SYRK), the tiles
+// below them (GEMM), or both.
+enum { UPD_DIAG = 1, UPD_BELOW = 2, UPD_ALL = 3 };
+
 void describe_update(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, int64_t k, int64_t n0,
-                     int64_t n1) {
+                     int64_t n1, int part = UPD_ALL) {
   const int64_t b = L.b, T = L.T;
   if (n0 >= n1) return;
   const bool mixed = is_mixed(prec), split = is_bf16(prec);
@@ -433,10 +437,10 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
   const double bd = (double)b;
   double syrk_flops = 0.0, gemm_flops = 0.0;
   for (int64_t nn = n0; nn < n1; ++nn) {
-    syrk_flops += bd * bd * (bd + 1.0);
-    gemm_flops += 2.0 * (double)(T - nn - 1) * bd * bd * bd;
+    if (part & UPD_DIAG) syrk_flops += bd * bd * (bd + 1.0);
+    if (part & UPD_BELOW) gemm_flops += 2.0 * (double)(T - nn - 1) * bd * bd * bd;
   }
-  if (mixed) {
+  if (mixed && (part & UPD_DIAG)) {
     // the SYRK into the float64 diagonal tiles, float64 products of the float32 panel,
     // both operands m-contiguous from the transposed panel tiles
     const char* ptk = (const char*)panel_t_set(L, w, k);
@@ -457,10 +461,11 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
   for (int64_t nn = n0; nn < n1; ++nn) {
     for (int64_t m = nn; m < T; ++m) {
       if (m == nn) {
-        if (mixed) continue;
+        if (mixed || !(part & UPD_DIAG)) continue;
         double* Cm = L.diag(K, m);
         P.job(Cm, b, Cm, b, b, b, -1.0, 1.0, JOB_LOWER_ONLY);
       } else {
+        if (!(part & UPD_BELOW)) continue;
         void* Cmn = L.off(K, m, nn);
         P.job(Cmn, b, Cmn, b, b, b, -1.0, 1.0, mixed ? JOB_C_F32 : 0);
       }
@@ -477,10 +482,12 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // (SYRK on diagonal tiles, GEMM elsewhere) as batched launches.  Without the look-ahead
 // all of it goes to the caller's stream in that order, one update launch per step.
 //
-// Look-ahead (default): each step's update is issued as the next block column (U1) and the
-// remaining columns (U2).  The factorisation of diagonal tile k+1 and the solve of its
-// panel run on the auxiliary stream as soon as U1 is done, overlapping U2 on the caller's
-// stream; events order the two (e1(k): U1 of step k done, e2(k): panel k solved).  The
+// Look-ahead (default): each step's update is issued as block column k+1 (U1) and the
+// remaining columns (U2), in the mixed modes with diagonal tile k+1 first on its own (U0).
+// The factorisation of diagonal tile k+1 runs on the auxiliary stream as soon as U1 (mixed:
+// U0, beside U1) is done, and the solve of its panel once U1 is done, overlapping U2 on
+// the caller's stream; events order the two (e0(k): U0 of step k done, e1(k): U1 done,
+// e2(k): panel k solved).  The
 // two streams touch disjoint tiles: U2 reads block column k and writes columns >= k+2,
 // the look-ahead work reads and writes block column k+1, diagonal tile k+1 and its
 // inverse, the panel copy and the operands of the next update built from panel k+1 (its
@@ -495,7 +502,7 @@ void describe_update(Program& P, const TileLayout& L, void* K, int prec, const C
 // step j multiplies block row j of W by the block inverse W_jj and subtracts
 // P_j (W_jj W_j) from the rows below, P_j being the block column of L below the
 // diagonal block; that update shares its launch with the trailing update P_j P_j^T.
-int chol_events_needed(int64_t T) { return 1 + 2 * (int)T; }
+int chol_events_needed(int64_t T) { return 1 + 3 * (int)T; }
 
 // Schedule of the factorisation (gpr_set_schedule): GPR_SCHEDULE_STREAM (every launch on the
 // caller's stream), GPR_SCHEDULE_LOOKAHEAD (two streams, the default) or GPR_SCHEDULE_DEVICE
@@ -505,8 +512,7 @@ std::atomic<int> g_schedule{GPR_SCHEDULE_LOOKAHEAD};
 
 void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const CholWs& w, bool lookahead) {
   const int64_t T = L.T;
-  auto diag_and_panel = [&](int64_t k) {
-    describe_diag(P, L, K, w, k);
+  auto panel = [&](int64_t k) {
     describe_panel_copy(P, L, K, prec, w, k);
     if (k < T - 1) {
       P.gemm_begin(is_mixed(prec));
@@ -516,8 +522,13 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
     describe_transpose(P, L, K, prec, w, k);
     describe_split(P, L, K, prec, w, k);
   };
-  auto e1 = [](int64_t k) { return 1 + 2 * (int)k; };
-  auto e2 = [](int64_t k) { return 2 + 2 * (int)k; };
+  auto diag_and_panel = [&](int64_t k) {
+    describe_diag(P, L, K, w, k);
+    panel(k);
+  };
+  auto e0 = [](int64_t k) { return 1 + 3 * (int)k; };   // step k's update of diagonal tile k+1 done
+  auto e1 = [](int64_t k) { return 2 + 3 * (int)k; };   // step k's update of block column k+1 done
+  auto e2 = [](int64_t k) { return 3 + 3 * (int)k; };   // panel k solved
   unsigned long long* info = w.info;
   P.on(0);
   P.kernel([=](hipStream_t s) { return launch_fill_u64(info, ~0ull, 2, s); }, {}, {span(info, 16)});
@@ -536,15 +547,33 @@ void describe_cholesky(Program& P, const TileLayout& L, void* K, int prec, const
   P.wait(0);
   diag_and_panel(0);
   P.record(e2(0));
+  // The mixed modes update the float64 diagonal tiles in a launch of their own (U0), so the
+  // factorisation of diagonal tile k+1 can start beside U1.  In float64 the diagonal tile's
+  // SYRK shares U1's launch: on its own it would fill only half the GPU (its lower
+  // macro tiles), which costs about what the overlap gains.
+  const bool split_u0 = is_mixed(prec);
   for (int64_t k = 0; k + 1 < T; ++k) {
     P.on(0);
     P.wait(e2(k));
-    describe_update(P, L, K, prec, w, k, k + 1, k + 2);   // U1: block column k+1
+    if (split_u0) {
+      describe_update(P, L, K, prec, w, k, k + 1, k + 2, UPD_DIAG);    // U0: diagonal tile k+1
+      P.record(e0(k));
+      describe_update(P, L, K, prec, w, k, k + 1, k + 2, UPD_BELOW);   // U1: the rest of block column k+1
+    } else {
+      describe_update(P, L, K, prec, w, k, k + 1, k + 2);              // U1: block column k+1
+    }
     P.record(e1(k));
-    describe_update(P, L, K, prec, w, k, k + 2, T);       // U2: the remaining columns
+    describe_update(P, L, K, prec, w, k, k + 2, T);                    // U2: the remaining columns
     P.on(1);
-    P.wait(e1(k));
-    diag_and_panel(k + 1);
+    if (split_u0) {
+      P.wait(e0(k));
+      describe_diag(P, L, K, w, k + 1);   // beside U1: it reads only diagonal tile k+1
+      P.wait(e1(k));
+    } else {
+      P.wait(e1(k));
+      describe_diag(P, L, K, w, k + 1);
+    }
+    panel(k + 1);
     P.record(e2(k + 1));
   }
   P.on(0);

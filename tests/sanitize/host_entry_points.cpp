@@ -55,7 +55,7 @@ int main() {
       EXPECT(gpr_cholesky_schedule_check(T * 64, 64, prec, -1, rep) == GPR_OK);
       EXPECT(rep[5] == 0);
       if (T >= 3) {
-        EXPECT(gpr_cholesky_schedule_check(T * 64, 64, prec, 1, rep) == GPR_OK);
+        EXPECT(gpr_cholesky_schedule_check(T * 64, 64, prec, 2, rep) == GPR_OK);   // block column 1 updated
         EXPECT(rep[5] > 0);
       }
     }

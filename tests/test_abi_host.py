@@ -86,7 +86,8 @@ def test_cholesky_schedule_has_no_unordered_conflicts(lib, prec):
             assert r["launches_main"] >= 1 and r["launches_aux"] >= 1
             if T >= 3:
                 assert r["concurrent_pairs"] > 0, (b, T, r)
-            assert r["waits"] == 2 * T
+            # per step: e1 (auxiliary; and e0 in the mixed modes), e2 (caller's); start and end
+            assert r["waits"] == (2 * T if prec == "fp64" else 3 * T - 1)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
@@ -95,12 +96,20 @@ def test_cholesky_schedule_every_wait_is_needed(lib, prec):
     waits for leaves a conflicting pair unordered."""
     T, b = 8, 128
     assert lib.gpr_cholesky_schedule_check(T * b, b, prec)["conflicts"] == 0
-    waited = [0] + [2 + 2 * k for k in range(T)] + [1 + 2 * k for k in range(T - 1)]
+    # event 0: start; 1 + 3k: diagonal tile k+1 updated by step k; 2 + 3k: the rest of
+    # block column k+1 updated; 3 + 3k: panel k solved
+    # (the last step's U1 covers no tile -- block column T-1 has none below its diagonal
+    # tile -- so its event 2 + 3(T-2) orders nothing beyond event 1 + 3(T-2))
+    waited = [0] + [3 + 3 * k for k in range(T)]
+    if prec == "fp64":   # one update launch for block column k+1: the diagonal tile waits for e1
+        waited += [2 + 3 * k for k in range(T - 1)]
+    else:
+        waited += [1 + 3 * k for k in range(T - 1)] + [2 + 3 * k for k in range(T - 2)]
     for ev in waited:
         r = lib.gpr_cholesky_schedule_check(T * b, b, prec, ev)
         assert r["conflicts"] > 0, (ev, r)
     # an event nobody waits for changes nothing
-    assert lib.gpr_cholesky_schedule_check(T * b, b, prec, 1 + 2 * (T - 1))["conflicts"] == 0
+    assert lib.gpr_cholesky_schedule_check(T * b, b, prec, 1 + 3 * (T - 1))["conflicts"] == 0
 
 
 def test_cholesky_schedule_check_arguments(lib):
