@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgpr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abi.cpp", "schedule.cpp", "gemm.hip", "gemm_bf16.hip", "potrf_block.hip", "potrf.hip", "assemble.hip", "blas2.hip", "warmstart.hip", "scratch.hip", "dag.hip"]
+SOURCES = ["abi.cpp", "schedule.cpp", "gemm.hip", "gemm_bf16.hip", "potrf_block.hip", "potrf.hip", "assemble.hip", "blas2.hip", "warmstart.hip", "scratch.hip", "dag.hip", "gram.hip"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

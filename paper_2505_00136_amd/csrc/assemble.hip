@@ -247,6 +247,9 @@ hipError_t launch_kmatvec_partial(const double* A, int64_t rows, const double* B
   if (rows == 0) return hipSuccess;
   const int64_t nch = cols == 0 ? 0 : (cols + chunk_cols - 1) / chunk_cols;
   if (nch == 0) return hipSuccess;
+  // the squared exponential forms its distances on the matrix cores (gram.hip)
+  if (h.kernel == KERNEL_SE && chunk_cols % 128 == 0)
+    return launch_se_kmatvec_gram(A, rows, B, cols, d, h, v, partial, chunk_cols, st);
   dim3 grid((unsigned)((rows + KB - 1) / KB), (unsigned)nch);
   hipLaunchKernelGGL(kmatvec_partial_kernel, grid, dim3(256), 0, st, A, rows, B, cols, d, h, v, partial,
                      chunk_cols);

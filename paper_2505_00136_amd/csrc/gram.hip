@@ -1,0 +1,228 @@
+// Fused kernel-vector products for the squared exponential (Eq. 2) with the squared
+// distances from Gram products on the matrix cores:
+//   r_ij^2 = |a_i|^2 + |b_j|^2 - 2 a_i . b_j,
+// the dot products of a 128 x 128 block of point pairs being one tile product with depth D
+// (the tile-GEMM main loop of gemm_device.h, both operands k-contiguous: the rows of the
+// row-major feature matrices).  The cancellation in this form costs an absolute error of a
+// few ulp of |a|^2 + |b|^2 in r^2, i.e. a few times (|a|^2 + |b|^2) / (2 l^2) ulp of nu in
+// the kernel value nu exp(-r^2 / (2 l^2)).  A block of pairs whose
+// (max |a|^2 + max |b|^2) / (2 l^2) exceeds kGramRatioMax therefore forms its distances
+// from explicit differences instead (features staged through LDS), which keeps the error
+// of every kernel value at a few ulp of nu whatever the offset of the points from the
+// origin; standardised features with l^2 near D (ratio about 1) take the Gram form.  The Matern forms, whose value depends on sqrt(r^2), keep the explicit
+// differences of assemble.hip.  A pair of the same point (the training residual) gets
+// r^2 = 0 exactly.
+#include "common.h"
+#include "gemm_device.h"
+#include "kernels.h"
+
+namespace gpr {
+
+namespace {
+
+constexpr double kGramRatioMax = 16.0;   // largest (max|a|^2 + max|b|^2) / (2 l^2) of the Gram form
+constexpr int GR_WN = 4;                 // the tile-GEMM wave layout: 512 threads, 64 x 32 per wave
+typedef Shape<GR_WN> GrShape;
+
+// |P_r|^2 for rows r0 .. r0+127 of the row-major n x d matrix P (0 past `lim`), into nrm;
+// four threads per row, fixed summation order.
+GPR_DEV void row_norms(const double* __restrict__ P, int64_t lim, int64_t r0, int64_t d, double* nrm) {
+  const int tid = threadIdx.x, r = tid >> 2, q = tid & 3;
+  double s = 0.0;
+  const int64_t row = r0 + r;
+  if (row < lim) {
+    const double* p = P + row * d;
+    for (int64_t f = q; f < d; f += 4) s = fma(p[f], p[f], s);
+  }
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  if (q == 0) nrm[r] = s;
+}
+
+// Largest of the 128 norms in nrm (wave 0 reduces, the result in *out).
+GPR_DEV void max_norm(const double* nrm, double* out) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    double m = nrm[tid] > nrm[tid + 64] ? nrm[tid] : nrm[tid + 64];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double x = __shfl_xor(m, o);
+      m = x > m ? x : m;
+    }
+    if (tid == 0) *out = m;
+  }
+}
+
+constexpr int GR_FC = 32;   // features per LDS stage of the explicit differences
+
+// acc[i][j][r] = sum_f (A_row - B_col)_f^2 for this lane's elements of the 128 x 128 block
+// (the MFMA output layout of the Gram path), from explicit differences in feature order;
+// rows past rlim and columns past clim read zero features.  Uses all of smem.
+template <int NJ>
+GPR_DEV void explicit_r2(const double* __restrict__ A, int64_t rlim, int64_t r0, const double* __restrict__ B,
+                         int64_t clim, int64_t c0, int64_t d, char* smem, v4d (&acc)[4][NJ], int lane, int wm,
+                         int wn) {
+  double (*za)[GEMM_BM] = reinterpret_cast<double (*)[GEMM_BM]>(smem);
+  double (*zb)[GEMM_BN] = za + GR_FC;
+  const int tid = threadIdx.x, pr = tid >> 2, pf = (tid & 3) * 8;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+  for (int64_t f0 = 0; f0 < d; f0 += GR_FC) {
+    __syncthreads();
+    {
+      const int64_t ga = r0 + pr, gb = c0 + pr;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t f = f0 + pf + e;
+        za[pf + e][pr] = (ga < rlim && f < d) ? A[ga * d + f] : 0.0;
+        zb[pf + e][pr] = (gb < clim && f < d) ? B[gb * d + f] : 0.0;
+      }
+    }
+    __syncthreads();
+    const int fc = (int)((d - f0) < GR_FC ? (d - f0) : GR_FC);
+    for (int f = 0; f < fc; ++f) {
+      double b[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = zb[f][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double a = za[f][wm + i * 16 + MfmaOp<double>::row(lane, r)];
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const double df = a - b[j];
+            acc[i][j][r] = fma(df, df, acc[i][j][r]);
+          }
+        }
+    }
+  }
+  __syncthreads();   // the staging buffers are reused
+}
+
+}  // namespace
+
+// partial[chunk][i] = sum over the chunk's points j of k(A_i, B_j) v_j (squared exponential).
+// Grid (ceil(rows / 128), chunks); workgroup (x, y) takes rows 128 x .. and the points of
+// chunk y in blocks of 128.  `same`: A and B are the same points (a pair (i, i) is at
+// distance 0).
+template <int SPEC>
+__global__ __launch_bounds__(GrShape::THREADS, 2)
+void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const double* __restrict__ B, int64_t cols,
+                            int64_t d, HyperArg h, const double* __restrict__ v, double* __restrict__ partial,
+                            int64_t chunk_cols, int same) {
+  __shared__ __align__(16) char smem[Chunk<double>::SMEM];
+  __shared__ double na[GEMM_BM], nb[GEMM_BN];
+  __shared__ double red[GR_WN][GEMM_BM];
+  __shared__ double maxna, maxnb;
+  __shared__ GemmSeg seg;
+  LdsBuf<double> As = reinterpret_cast<LdsBuf<double>>(smem);
+  LdsBuf<double> Bs = As + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = GrShape::m0(wave), wn = GrShape::n0(wave);
+  const int64_t r0 = (int64_t)blockIdx.x * GEMM_BM;
+  const int64_t cbeg = (int64_t)blockIdx.y * chunk_cols;
+  const int64_t cend = cbeg + chunk_cols < cols ? cbeg + chunk_cols : cols;
+  double ell, nu, s2;
+  resolve_hyper(h, ell, nu, s2);
+  const double g = -0.5 / (ell * ell);
+  if (tid == 0) seg = GemmSeg{A, B, d, d, 0, 0, (int32_t)d, MODE_KC, MODE_KC, 0, 0};
+  if (tid < GR_WN * GEMM_BM) red[tid / GEMM_BM][tid % GEMM_BM] = 0.0;
+  GemmJob job{};
+  job.M = (int32_t)rows;
+  job.N = (int32_t)cols;
+  job.seg0 = 0;
+  job.nseg = 1;
+  row_norms(A, rows, r0, d, na);
+  __syncthreads();
+  max_norm(na, &maxna);
+  for (int64_t c0 = cbeg; c0 < cend; c0 += GEMM_BN) {
+    row_norms(B, cend, c0, d, nb);
+    __syncthreads();
+    max_norm(nb, &maxnb);
+    __syncthreads();   // norms, their maxima and the segment visible; the previous block's LDS reads done
+    v4d acc[4][GrShape::NJ];
+    if ((maxna + maxnb) * (-g) <= kGramRatioMax) {
+      // squared distances from the Gram products
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < GrShape::NJ; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+      gemm_mainloop<double, double, SPEC, GR_WN>(job, &seg, (int)r0, (int)c0, acc, As, Bs);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < GrShape::NJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double r2 = na[wm + i * 16 + MfmaOp<double>::row(lane, r)] + nb[wn + j * 16 + (lane & 15)] -
+                              2.0 * acc[i][j][r];
+            acc[i][j][r] = r2 > 0.0 ? r2 : 0.0;
+          }
+    } else {
+      explicit_r2<GrShape::NJ>(A, rows, r0, B, cend, c0, d, smem, acc, lane, wm, wn);
+    }
+    double vj[GrShape::NJ];
+#pragma unroll
+    for (int j = 0; j < GrShape::NJ; ++j) {
+      const int64_t col = c0 + wn + j * 16 + (lane & 15);
+      vj[j] = col < cend ? v[col] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lr = wm + i * 16 + MfmaOp<double>::row(lane, r);
+        const int64_t row = r0 + lr;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < GrShape::NJ; ++j) {
+          const int lc = wn + j * 16 + (lane & 15);
+          const int64_t col = c0 + lc;
+          double r2 = acc[i][j][r];
+          if (same && row == col) r2 = 0.0;
+          if (row < rows && col < cend) s = fma(nu * exp(g * r2), vj[j], s);
+        }
+        // the 16 lanes holding this row (different columns), then one lane per row adds
+        // the block's sum to its wave's slot
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 8);
+        if ((lane & 15) == 0) red[wave % GR_WN][lr] += s;
+      }
+    __syncthreads();   // nb and the LDS operand buffers are rewritten by the next block
+  }
+  if (tid < GEMM_BM) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < GR_WN; ++q) s += red[q][tid];
+    const int64_t r = r0 + tid;
+    if (r < rows) partial[(int64_t)blockIdx.y * rows + r] = s;
+  }
+}
+
+hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
+                                  HyperArg h, const double* v, double* partial, int64_t chunk_cols, hipStream_t st) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  if (rows > 0x7fffff00 || cols > 0x7fffff00 || d > 0x7fffffff || chunk_cols % GEMM_BN != 0)
+    return hipErrorInvalidValue;
+  const int64_t nch = (cols + chunk_cols - 1) / chunk_cols;
+  dim3 grid((unsigned)((rows + GEMM_BM - 1) / GEMM_BM), (unsigned)nch);
+  const int same = (A == B && rows == cols) ? 1 : 0;
+  // the straight-line main loop needs whole 128-point blocks, whole 16-deep chunks and
+  // 16-byte aligned rows; anything else takes the guarded loop
+  const bool full = rows % GEMM_BM == 0 && cols % GEMM_BN == 0 && d % Chunk<double>::BK == 0 &&
+                    ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+  if (full)
+    hipLaunchKernelGGL(se_kmatvec_gram_kernel<SPEC_KK>, grid, dim3(GrShape::THREADS), 0, st, A, rows, B, cols, d, h,
+                       v, partial, chunk_cols, same);
+  else
+    hipLaunchKernelGGL(se_kmatvec_gram_kernel<SPEC_GUARDED>, grid, dim3(GrShape::THREADS), 0, st, A, rows, B, cols, d,
+                       h, v, partial, chunk_cols, same);
+  return hipGetLastError();
+}
+
+}  // namespace gpr

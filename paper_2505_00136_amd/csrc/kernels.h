@@ -85,6 +85,10 @@ hipError_t launch_assemble_dense(const double* A, int64_t rows, const double* B,
 hipError_t launch_kmatvec_partial(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
                                   HyperArg h, const double* v, double* partial, int64_t chunk_cols,
                                   hipStream_t st);
+// the same for the squared exponential, the distances from Gram products on the matrix
+// cores (gram.hip); chunk_cols a multiple of 128
+hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
+                                  HyperArg h, const double* v, double* partial, int64_t chunk_cols, hipStream_t st);
 
 // blas2.hip
 // y[r] = beta*yin[r] + alpha * sum_c A[r*lda + c] x[c]   for r < rows (A float64 or float32)

@@ -10,7 +10,14 @@ with float64 diagonal tiles and three refinement sweeps, from theta = (0, 0, log
   must equal the device-side Adam of gpr_optimize in the same precision (the same
   kernels compute every NLML and gradient; only the Adam arithmetic differs, by
   rounding), must stay within the mixed-mode bounds of the float64 trajectory (NLML
-  1e-6 relative, theta 1e-4), and must lower the NLML.
+  1e-6 relative, theta 1e-4), and must lower the NLML.  The two Adam updates round
+  differently by an ulp of theta now and then.  In float64 that stays at about 1e-15
+  (compared at 1e-12);
+  in float32 the trailing updates amplify it once the optimiser nears its minimum: the
+  two float32 traces agree to 1e-14 for the first 30 steps and then part at about a
+  factor 10 per 5 steps, to about 1e-9 after 50, and the float32 comparison is split
+  accordingly (1e-12 on the first 26 NLMLs, 1e-7 on the rest and on theta, an order
+  below the float32-to-float64 bound).
 """
 import math
 
@@ -77,10 +84,9 @@ def _device_adam(ds, prec):
     return np.array(th), np.array(tr)
 
 
-def test_fifty_adam_steps_through_the_autograd_function(ds):
+def _autograd_adam(ds, prec):
     from paper_2505_00136_amd.gp import GP, nlml
-    print("[differentiation] autograd + torch.optim.Adam, float32", flush=True)
-    gp = GP(ds.Z, ds.y, hyper=tuple(math.exp(v) for v in THETA0), tile=TILE, prec="fp32")
+    gp = GP(ds.Z, ds.y, hyper=tuple(math.exp(v) for v in THETA0), tile=TILE, prec=prec)
     theta = torch.tensor(THETA0, dtype=torch.float64, requires_grad=True)
     opt = torch.optim.Adam([theta], lr=LR, betas=(0.9, 0.999), eps=1e-8)
     trace = []
@@ -91,12 +97,21 @@ def test_fifty_adam_steps_through_the_autograd_function(ds):
         opt.step()
         trace.append(loss.item())
     trace.append(nlml(theta.detach(), gp).item())
-    trace = np.array(trace)
+    return theta.detach().numpy(), np.array(trace)
+
+
+def test_fifty_adam_steps_through_the_autograd_function(ds):
+    print("[differentiation] autograd + torch.optim.Adam, float32 and float64", flush=True)
+    theta, trace = _autograd_adam(ds, "fp32")
+    ta64, tra64 = _autograd_adam(ds, "fp64")
     print("[differentiation] device Adam, float32 and float64", flush=True)
     th32, tr32 = _device_adam(ds, "fp32")
     th64, tr64 = _device_adam(ds, "fp64")
-    np.testing.assert_allclose(theta.detach().numpy(), th32, rtol=1e-9, atol=1e-12)
-    np.testing.assert_allclose(trace, tr32, rtol=1e-9)
+    np.testing.assert_allclose(tra64, tr64, rtol=1e-12)
+    np.testing.assert_allclose(ta64, th64, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(trace[:26], tr32[:26], rtol=1e-12)
+    np.testing.assert_allclose(trace, tr32, rtol=1e-7)
+    np.testing.assert_allclose(theta, th32, rtol=1e-7, atol=1e-12)
     np.testing.assert_allclose(tr32, tr64, rtol=1e-6)
     np.testing.assert_allclose(th32, th64, rtol=0, atol=1e-4)
     assert tr32[-1] < tr32[0] and np.all(np.isfinite(tr32))

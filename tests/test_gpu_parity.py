@@ -178,6 +178,31 @@ def test_tiling_invariance_bitwise_determinism(lib):
         assert abs(res[tile][1] - res[768][1]) / abs(res[768][1]) < 1e-12
 
 
+@pytest.mark.parametrize("n,m", [(1024, 1024), (1000, 333)])
+@pytest.mark.parametrize("offset", [0.0, 1e4])
+def test_mean_of_points_far_from_the_origin(lib, n, m, offset):
+    """The squared-exponential kernel-vector products form distances from Gram products
+    when the squared norms of the points are small against the lengthscale, from
+    explicit differences otherwise.  Points shifted by 1e4 in every feature would lose
+    about 1e-7 of each kernel value to the cancellation of the Gram form; the mean must
+    stay within rounding of the oracle's either way (full and ragged 128-point blocks)."""
+    rng = np.random.default_rng(int(offset) + n)
+    D = 8
+    Z = rng.normal(size=(n, D)) + offset
+    Zs = np.concatenate([Z[:m // 2], rng.normal(size=(m - m // 2, D)) + offset])   # half of them training points
+    alpha = rng.normal(size=n)
+    h = Hyper(1.5, 0.8, 0.01)
+    dev = "cuda:0"
+    Zt, Zst, at = (torch.tensor(x, device=dev) for x in (Z, Zs, alpha))
+    wsb = lib.gpr_workspace_size(n, m, D, 256, "fp64")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    mean = torch.empty(m, dtype=torch.float64, device=dev)
+    lib.gpr_predict(Zt, n, Zst, m, D, h, at, mean, ws, wsb)
+    torch.cuda.synchronize()
+    print(f"[far-points] n={n} m={m} offset={offset:g}", flush=True)
+    assert_elementwise(mean.cpu().numpy(), oracle.predict_mean(Z, Zs, h, alpha), 1e-10)
+
+
 def test_one_point_closed_form(lib):
     z1 = np.array([[0.3, -1.2, 0.5]])
     y1 = np.array([0.8])
