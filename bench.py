@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Cholesky TFLOP/s + train/predict s, n=65536 D=128: FP64 vs mixed @ stated err"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-SPLIT_PRODUCTS = {"bf16x3": 3, "bf16x6": 6}
+SPLIT_PRODUCTS = {"bf16x3": 3, "bf16x6": 6, "bf16x3_trtri": 3, "bf16x6_trtri": 6, "bf16x3_trace": 3, "bf16x6_trace": 6}
 WORKLOADS = {
     # the configuration the metric is quoted on: n=65536, D=128 lagged inputs, 8192 test points, tile 2048
     "n65536_d128": dict(n=65536, m=8192, D=128, tile=2048, seed=3),
@@ -63,6 +63,8 @@ TIMED_KERNELS = {
     "fp64_trtri": ("gemm_trtri_kernel<double, *>", "f64"), "fp32_trtri": ("gemm_trtri_kernel<float, *>", "f32"),
     "fp64_trace": ("gemm_trace_kernel<double, 3>", "f64"), "fp32_trace": ("gemm_trace_kernel<float, 3>", "f32"),
     "bf16x3": ("gemm_bf16x_t256_kernel<3>", "bf16"), "bf16x6": ("gemm_bf16x_t256_kernel<6>", "bf16"),
+    "bf16x3_trtri": ("gemm_bf16x_trtri_t256_kernel<3>", "bf16"), "bf16x6_trtri": ("gemm_bf16x_trtri_t256_kernel<6>", "bf16"),
+    "bf16x3_trace": ("gemm_bf16x_trace_t256_kernel<3>", "bf16"), "bf16x6_trace": ("gemm_bf16x_trace_t256_kernel<6>", "bf16"),
 }
 KIND_ROLE = {"fp64": "trailing SYRK+GEMM update of a Cholesky step", "fp32": "trailing SYRK+GEMM update of a Cholesky step",
              "fp64_trtri": "step of the triangular inversion L^-1 (gradient)",
@@ -70,7 +72,11 @@ KIND_ROLE = {"fp64": "trailing SYRK+GEMM update of a Cholesky step", "fp32": "tr
              "fp64_trace": "K^-1 block-row product fused with the gradient reduction",
              "fp32_trace": "K^-1 block-row product fused with the gradient reduction",
              "bf16x3": "trailing update of a Cholesky step from split-bf16 planes",
-             "bf16x6": "trailing update of a Cholesky step from split-bf16 planes"}
+             "bf16x6": "trailing update of a Cholesky step from split-bf16 planes",
+             "bf16x3_trtri": "step of the triangular inversion L^-1 (gradient) from split-bf16 planes",
+             "bf16x6_trtri": "step of the triangular inversion L^-1 (gradient) from split-bf16 planes",
+             "bf16x3_trace": "K^-1 block-row product fused with the gradient reduction, split-bf16 planes",
+             "bf16x6_trace": "K^-1 block-row product fused with the gradient reduction, split-bf16 planes"}
 
 
 def source_digest(paths) -> str:

@@ -230,7 +230,10 @@ GPR_API int gpr_nlml(const void* L_tiles, int64_t n, int64_t tile, int prec, con
  * (Matern kernels, s = r / l: dK/dlog l = nu s exp(-s), 3 nu s^2 exp(-sqrt(3) s) and
  * (5/3) nu s^2 (1 + sqrt(5) s) exp(-sqrt(5) s) for 1/2, 3/2 and 5/2).
  * K^{-1} = L^{-T} L^{-1} is formed tile by tile from the factor and consumed inside
- * the reduction.  L_tiles is destroyed: region O is overwritten with the
+ * the reduction.  The products run in float64 (GPR_FP64), float32 (GPR_FP32, and the
+ * split modes when the tile is not a multiple of 256), or as the mode's split-bfloat16
+ * products (GPR_BF16X3 / GPR_BF16X6, tiles a multiple of 256); the contraction with
+ * the kernel weights is float64.  L_tiles is destroyed: region O is overwritten with the
  * strictly-lower tiles of L^{-1}.  trainable: host[3] (0 = that entry is returned as 0,
  * NULL = all trainable).  grad_log: device[3] (out). */
 GPR_API int gpr_nlml_grad(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, void* L_tiles, int64_t tile,
@@ -322,7 +325,12 @@ GPR_API int gpr_timing_enable(int on);
  *   6/7  float64/float32 K^{-1} product fused with the gradient reduction (as kind 4/5
  *        for tile pairs off the diagonal; a diagonal tile pair is symmetric and computed
  *        on and below its diagonal only: b^2 (b+1) from full tiles, b (b+1)(b+2)/3 from
- *        two triangular tiles; all launches of one gradient add up to about n^3 / 3).
+ *        two triangular tiles; all launches of one gradient add up to about n^3 / 3);
+ *   8/9  bf16x3/bf16x6 step of the triangular inversion (split modes with tiles a
+ *        multiple of 256; the same algorithmic count as kind 4/5, although these launches
+ *        multiply the triangular tiles in full);
+ *   10/11 bf16x3/bf16x6 K^{-1} product fused with the gradient reduction (as 8/9, the
+ *        count of kind 6/7).
  * Resets that kind's record.  All three are host outputs. */
 GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops);
 

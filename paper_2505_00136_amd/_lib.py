@@ -299,7 +299,8 @@ def gpr_mlp_train_step(params, adam_m, adam_v, t, X, Y, batch, lr, beta1, beta2,
 
 
 TIMING_KINDS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp64_trtri": 4, "fp32_trtri": 5,
-                "fp64_trace": 6, "fp32_trace": 7}
+                "fp64_trace": 6, "fp32_trace": 7, "bf16x3_trtri": 8, "bf16x6_trtri": 9, "bf16x3_trace": 10,
+                "bf16x6_trace": 11}
 
 
 def gpr_timing_read(kind="fp64"):

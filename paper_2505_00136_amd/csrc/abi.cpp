@@ -890,6 +890,9 @@ struct GradWs {
   void* panel;      // block column of L with each tile transposed: (T-1) b x b tiles
   void* row;        // copy of one block row of the residual: (T-1) b x b tiles
   float* w32;       // T b x b (mixed)
+  uint16_t* pa;     // split modes, tiles a multiple of 256: bfloat16 planes of T tiles each
+  uint16_t* pb;     //   (A and B operands of the products), plane stride pstride elements
+  int64_t pstride;
   double* partial;  // [trace workgroups][3]
   int64_t partial_wg;
   double* u;        // r^2 / (2 l^2) of every lower tile pair: T (T+1) / 2 float64 tiles
@@ -990,13 +993,121 @@ void describe_lauum_trace(Program& P, const TileLayout& L, void* K, int prec, co
   }
 }
 
+// The inversion of describe_trtri from split-bfloat16 planes (tiles a multiple of 256):
+// before each launch the operand tiles are split into planes in the tiled layout, the A
+// operands as stored, the B operands transposed (the kernels take C = A B^T with both
+// operands k-contiguous), and the triangular tiles W_jj as full tiles with their zeros.
+// The planes are copies, so the products may overwrite their sources: step j splits
+//   W_jj and R_jc^T (c < j), then X_jc = W_jj R_jc in place;
+//   L_ij (i > j), X_jc^T and W_jj^T, then R_ic -= L_ij X_jc and R_ij = -L_ij W_jj in place.
+void describe_trtri_split(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
+  const int64_t b = L.b, T = L.T, bb = b * b, ps = w.pstride;
+  const int np = prec == GPR_BF16X6 ? 3 : 2;
+  const int kind = prec == GPR_BF16X6 ? GEMM_KIND_BF16X6_TRTRI_T256 : GEMM_KIND_BF16X3_TRTRI_T256;
+  const double bd = (double)b, trmm = bd * bd * (bd + 1.0), gemm = 2.0 * bd * bd * bd;
+  uint16_t* const pa = w.pa;
+  uint16_t* const pb = w.pb;
+  auto split = [&](std::vector<const float*> src, bool trans, uint16_t* out) {
+    P.kernel([=](hipStream_t s) {
+      return launch_split_bf16_tiles(src.data(), (int64_t)src.size(), b, trans, out, ps, np, s);
+    });
+  };
+  auto seg = [&](const uint16_t* A, const uint16_t* B) {
+    P.seg(A, b, MODE_KC, B, b, MODE_KC, b, 0);
+    P.segs.back().pstrideA = P.segs.back().pstrideB = ps;
+  };
+  for (int64_t j = 0; j < T; ++j) {
+    const float* Wj = w.w32 + j * bb;
+    if (j > 0) {
+      std::vector<const float*> r(j);
+      for (int64_t c = 0; c < j; ++c) r[c] = (const float*)L.off(K, j, c);
+      split(r, true, pb);
+      split({Wj}, false, pa);
+      P.gemm_begin(1, kind, (double)j * trmm);
+      for (int64_t c = 0; c < j; ++c) {
+        P.job(L.off(K, j, c), b, nullptr, 0, b, b, 1.0, 0.0, JOB_C_F32);
+        seg(pa, pb + c * bb);
+      }
+      P.gemm_end();
+    }
+    if (j == T - 1) break;
+    std::vector<const float*> x(j + 1), col(T - j - 1);
+    for (int64_t c = 0; c < j; ++c) x[c] = (const float*)L.off(K, j, c);
+    x[j] = Wj;
+    for (int64_t i = j + 1; i < T; ++i) col[i - j - 1] = (const float*)L.off(K, i, j);
+    split(x, true, pb);
+    split(col, false, pa);
+    P.gemm_begin(1, kind, (double)(T - j - 1) * ((double)j * gemm + trmm));
+    for (int64_t i = j + 1; i < T; ++i) {
+      const uint16_t* Ai = pa + (i - j - 1) * bb;
+      for (int64_t c = 0; c < j; ++c) {
+        void* C = L.off(K, i, c);
+        P.job(C, b, C, b, b, b, -1.0, 1.0, JOB_C_F32);
+        seg(Ai, pb + c * bb);
+      }
+      P.job(L.off(K, i, j), b, nullptr, 0, b, b, -1.0, 0.0, JOB_C_F32);
+      seg(Ai, pb + j * bb);
+    }
+    P.gemm_end();
+  }
+}
+
+// describe_lauum_trace from split-bfloat16 planes: step k splits block row k of X = L^{-1}
+// transposed (X_ki^T, i < k, and W_kk^T), which is both operand sets of its products
+// X_ki^T X_kj, j <= i <= k.
+void describe_lauum_trace_split(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
+  const int64_t b = L.b, T = L.T, bb = b * b, ps = w.pstride;
+  const int np = prec == GPR_BF16X6 ? 3 : 2;
+  const int kind = prec == GPR_BF16X6 ? GEMM_KIND_BF16X6_TRACE_T256 : GEMM_KIND_BF16X3_TRACE_T256;
+  const double bd = (double)b;
+  const double full = 2.0 * bd * bd * bd, half = bd * bd * (bd + 1.0), tri3 = bd * (bd + 1.0) * (bd + 2.0) / 3.0;
+  uint16_t* const pb = w.pb;
+  for (int64_t k = 0; k < T; ++k) {
+    std::vector<const float*> x(k + 1);
+    for (int64_t i = 0; i < k; ++i) x[i] = (const float*)L.off(K, k, i);
+    x[k] = w.w32 + k * bb;
+    P.kernel([=](hipStream_t s) {
+      return launch_split_bf16_tiles(x.data(), (int64_t)x.size(), b, true, pb, ps, np, s);
+    });
+    const double kd = (double)k;
+    P.gemm_begin(1, kind, kd * (kd - 1.0) / 2.0 * full + 2.0 * kd * half + tri3);
+    for (int64_t i = 0; i <= k; ++i)
+      for (int64_t j = 0; j <= i; ++j) {
+        const int flags = (i == k ? JOB_TRACE_ALPHA : 0) | (i == j ? JOB_LOWER_ONLY : 0);
+        P.job(nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, flags, (int)i, (int)j);
+        P.seg(pb + i * bb, b, MODE_KC, pb + j * bb, b, MODE_KC, b, 0);
+        P.segs.back().pstrideA = P.segs.back().pstrideB = ps;
+      }
+    P.gemm_end();
+  }
+}
+
+// The split modes run the gradient's products from bfloat16 planes when the tiles suit the
+// 256 x 256 kernels (with the products of the update), float32 otherwise.
+bool grad_split(const TileLayout& L, int prec) { return is_bf16(prec) && bf16_tiled(L); }
+void describe_grad_inverse(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
+  if (grad_split(L, prec)) describe_trtri_split(P, L, K, prec, w);
+  else describe_trtri(P, L, K, prec, w);
+}
+void describe_grad_trace(Program& P, const TileLayout& L, void* K, int prec, const GradWs& w) {
+  if (grad_split(L, prec)) describe_lauum_trace_split(P, L, K, prec, w);
+  else describe_lauum_trace(P, L, K, prec, w);
+}
+
 GradWs carve_grad(Carve& c, const TileLayout& L, int prec) {
   GradWs w{};
   const int es = is_mixed(prec) ? 4 : 8;
   const size_t tiles = (size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * es;
-  w.panel = c.take<char>(tiles);
-  w.row = c.take<char>(tiles);
+  const bool split = grad_split(L, prec);
+  w.panel = split ? nullptr : c.take<char>(tiles);
+  w.row = split ? nullptr : c.take<char>(tiles);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.T * L.b * L.b) : nullptr;
+  if (split) {
+    const int np = prec == GPR_BF16X6 ? 3 : 2;
+    w.pstride = L.T * L.b * L.b;
+    w.pa = c.take<uint16_t>((size_t)np * w.pstride);
+    w.pb = c.take<uint16_t>((size_t)np * w.pstride);
+  }
   w.partial_wg = trace_workgroups(L);
   w.partial = c.take<double>((size_t)w.partial_wg * 3 + 3);
   w.u = c.take<double>((size_t)(L.T * (L.T + 1) / 2) * L.b * L.b);
@@ -1013,7 +1124,7 @@ int grad_impl(const double* Z, int64_t d, HyperArg h, void* K, const TileLayout&
   const size_t cap = ws_bytes > fixed ? ws_bytes - fixed : 0;
   const bool mixed = is_mixed(prec);
   if (mixed) HIPCHK(launch_convert_f64_f32(L.winv(K, 0), w.w32, L.T * L.b * L.b, st));
-  int rc = run_program([&](Program& P) { describe_trtri(P, L, K, prec, w); }, w.arena, cap, st);
+  int rc = run_program([&](Program& P) { describe_grad_inverse(P, L, K, prec, w); }, w.arena, cap, st);
   if (rc) return rc;
   HIPCHK(launch_halfdist_tiles(Z, L.n, d, h, L.b, L.T, w.u, st));
   if (w.apad) {
@@ -1027,7 +1138,7 @@ int grad_impl(const double* Z, int64_t d, HyperArg h, void* K, const TileLayout&
       [&](Program& P) {
         P.trace = &ta;
         P.trace_cap = w.partial_wg;
-        describe_lauum_trace(P, L, K, prec, w);
+        describe_grad_trace(P, L, K, prec, w);
       },
       w.arena, cap, st, &nwg);
   if (rc) return rc;
@@ -1039,8 +1150,8 @@ size_t grad_ws_bytes(const TileLayout& L, int prec) {
   Carve c(kSymWs);
   GradWs w = carve_grad(c, L, prec);
   Program P1, P2;
-  describe_trtri(P1, L, kSymK, prec, w);
-  describe_lauum_trace(P2, L, kSymK, prec, w);
+  describe_grad_inverse(P1, L, kSymK, prec, w);
+  describe_grad_trace(P2, L, kSymK, prec, w);
   return c.off + std::max(arena_bytes_of(P1), arena_bytes_of(P2));
 }
 
@@ -1109,8 +1220,8 @@ size_t table_bytes(const TileLayout& L, int64_t m, int prec) {
     Carve c(kSymWs);
     GradWs w = carve_grad(c, L, prec);
     Program P1, P2;
-    describe_trtri(P1, L, kSymK, prec, w);
-    describe_lauum_trace(P2, L, kSymK, prec, w);
+    describe_grad_inverse(P1, L, kSymK, prec, w);
+    describe_grad_trace(P2, L, kSymK, prec, w);
     t = std::max(t, std::max(arena_bytes_of(P1), arena_bytes_of(P2)));
   }
   return t;
@@ -1604,7 +1715,7 @@ GPR_API int gpr_timing_enable(int on) {
 
 GPR_API int gpr_timing_read(int kind, int64_t* launches, double* total_ms, double* algo_flops) {
   if (!launches || !total_ms || !algo_flops) return fail(GPR_ERR_ARG, "null pointer");
-  if (kind < 0 || kind > 7) return fail(GPR_ERR_ARG, "kind must be 0..7");
+  if (kind < 0 || kind > 11) return fail(GPR_ERR_ARG, "kind must be 0..11");
   std::lock_guard<std::mutex> lk(g_timing.mu);
   int64_t cnt = 0;
   double ms = 0.0, fl = 0.0;

@@ -184,9 +184,11 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
   if (kind == GEMM_KIND_BF16X3_T256 || kind == GEMM_KIND_BF16X6_T256)
     return launch_gemm_bf16_t256(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
+  if (kind == GEMM_KIND_BF16X3_TRTRI_T256 || kind == GEMM_KIND_BF16X6_TRTRI_T256)
+    return launch_gemm_bf16_trtri_t256(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
   if (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
     return launch_gemm_bf16(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
-  if (kind == GEMM_KIND_TRACE) return hipErrorInvalidValue;   // launched by launch_gemm_trace
+  if (gemm_kind_trace(kind)) return hipErrorInvalidValue;   // launched by launch_gemm_trace
   if (kind == GEMM_KIND_WIDEN) {
     if (spec == SPEC_KK) GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_KK>));
     else if (spec == SPEC_MM) GPR_GEMM_LAUNCH((gemm_widen_kernel<SPEC_MM>));

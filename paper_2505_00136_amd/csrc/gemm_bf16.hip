@@ -337,47 +337,42 @@ GPR_DEV void bt_mma(const bfraw* As, const bfraw* Bs, int wm, int wn, int frow, 
   }
 }
 
-// NPROD = 3 (hh, hm, mh) or 6 (+ hl, lh, mm).  Every job covers whole 256 x 256 macro
-// tiles, every segment is a pair of tiled-layout planes (lda = ldb = K, a multiple of 16,
-// no triangular skips); the host checks this before the launch.
-template <int NPROD>
-__global__ __launch_bounds__(BT_THREADS, 1)
-void gemm_bf16x_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
-  constexpr int NP = NPROD == 6 ? 3 : 2;
-  constexpr int HALF = NP * BT_M * BT_PITCH;   // the A (then the B) planes of one chunk
-  __shared__ __align__(16) bfraw smem[2 * 2 * HALF];
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+// Job and macro tile of workgroup `bid` of a 256 x 256 launch: the job whose workgroup
+// range holds bid, its macro tiles in 8 x 8 patches when both grid extents are multiples
+// of 8, row-major otherwise.
+GPR_DEV void t256_locate(const GemmJob* __restrict__ jobs, int njobs, int bid, GemmJob& job, int& m0, int& n0) {
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int midj = (lo + hi + 1) >> 1;
     if (jobs[midj].wg_begin <= bid) lo = midj; else hi = midj - 1;
   }
-  const GemmJob job = jobs[lo];
-  int m0, n0;
-  {
-    const int t = bid - job.wg_begin, tn = job.tiles_n, tm = job.M / BT_M;
-    if ((tn & 7) == 0 && (tm & 7) == 0) {
-      const int sb = t >> 6, w = t & 63, sbn = tn >> 3;
-      m0 = ((sb / sbn) * 8 + (w >> 3)) * BT_M;
-      n0 = ((sb % sbn) * 8 + (w & 7)) * BT_M;
-    } else {
-      m0 = (t / tn) * BT_M;
-      n0 = (t % tn) * BT_M;
-    }
+  job = jobs[lo];
+  const int t = bid - job.wg_begin, tn = job.tiles_n, tm = job.M / BT_M;
+  if ((tn & 7) == 0 && (tm & 7) == 0) {
+    const int sb = t >> 6, w = t & 63, sbn = tn >> 3;
+    m0 = ((sb / sbn) * 8 + (w >> 3)) * BT_M;
+    n0 = ((sb % sbn) * 8 + (w & 7)) * BT_M;
+  } else {
+    m0 = (t / tn) * BT_M;
+    n0 = (t % tn) * BT_M;
   }
-  if ((job.flags & JOB_LOWER_ONLY) && (m0 + BT_M - 1 < n0)) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
-  const int frow = lane & 31, fk = (lane >> 5) * 8;
+}
 
-  v16f acc[4][2];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+template <int NPROD>
+struct T256 {
+  static constexpr int NP = NPROD == 6 ? 3 : 2;
+  static constexpr int HALF = NP * BT_M * BT_PITCH;   // the A (then the B) planes of one chunk
+  static constexpr int SMEM = 2 * 2 * HALF;           // bfloat16 elements of LDS, double-buffered
+};
 
+// acc = the split-bfloat16 products of every segment of the job for the macro tile at
+// (m0, n0): wave `wave` owns rows wm .. wm+127 and columns wn .. wn+63 as 4 x 2
+// accumulators of 32 x 32.  smem: T256<NPROD>::SMEM elements.
+template <int NPROD>
+GPR_DEV void t256_mainloop(const GemmJob& job, const GemmSeg* __restrict__ segs, int m0, int n0, bfraw* smem,
+                           v16f (&acc)[4][2], int tid, int wm, int wn, int frow, int fk) {
+  constexpr int NP = T256<NPROD>::NP;
+  constexpr int HALF = T256<NPROD>::HALF;
   bfraw* const L0 = smem;              // chunk buffer 0: A planes, then B planes
   bfraw* const L1 = smem + 2 * HALF;   // chunk buffer 1
   bool primed = false;
@@ -425,8 +420,33 @@ void gemm_bf16x_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __r
       __syncthreads();
     }
   }
+}
 
-  // 32 x 32 f32 output: lane l, register r holds column l % 32, row 8 (r / 4) + 4 (l / 32) + r % 4
+// 32 x 32 float32 accumulator layout: lane l, register r holds column l % 32 and row
+// 8 (r / 4) + 4 (l / 32) + r % 4 of its block
+GPR_DEV int t256_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// C = alpha * (products) + beta * Cin for each job of whole 256 x 256 macro tiles.
+template <int NPROD>
+GPR_DEV void t256_body(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs, bfraw* smem) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  GemmJob job;
+  int m0, n0;
+  t256_locate(jobs, njobs, bid, job, m0, n0);
+  if ((job.flags & JOB_LOWER_ONLY) && (m0 + BT_M - 1 < n0)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+  const int frow = lane & 31, fk = (lane >> 5) * 8;
+
+  v16f acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  t256_mainloop<NPROD>(job, segs, m0, n0, smem, acc, tid, wm, wn, frow, fk);
+
   const bool c32 = job.flags & JOB_C_F32;
   const double alpha = job.alpha, beta = job.beta;
 #pragma unroll
@@ -435,7 +455,7 @@ void gemm_bf16x_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __r
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int row = m0 + wm + i * 32 + t256_row(lane, r);
         const int col = n0 + wn + j * 32 + (lane & 31);
         double v = alpha * (double)acc[i][j][r];
         if (c32) {
@@ -448,6 +468,199 @@ void gemm_bf16x_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __r
       }
 }
 
+// NPROD = 3 (hh, hm, mh) or 6 (+ hl, lh, mm).  Every job covers whole 256 x 256 macro
+// tiles, every segment is a pair of tiled-layout planes (lda = ldb = K, a multiple of 16,
+// no triangular skips); the host checks this before the launch.
+template <int NPROD>
+__global__ __launch_bounds__(BT_THREADS, 1)
+void gemm_bf16x_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  __shared__ __align__(16) bfraw smem[T256<NPROD>::SMEM];
+  t256_body<NPROD>(jobs, segs, njobs, smem);
+}
+
+// Steps of the triangular inversion L^{-1} of the gradient from split-bfloat16 planes
+// (same code as the update, its own symbol).
+template <int NPROD>
+__global__ __launch_bounds__(BT_THREADS, 1)
+void gemm_bf16x_trtri_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  __shared__ __align__(16) bfraw smem[T256<NPROD>::SMEM];
+  t256_body<NPROD>(jobs, segs, njobs, smem);
+}
+
+// The gradient reduction fused into the K^{-1} products (as gemm_trace_kernel in
+// gemm.hip, on 256 x 256 macro tiles of split-bfloat16 products): each job is the
+// contribution X_ki^T X_kj of block row k of X = L^{-1} to the K^{-1} tile (i, j) = (aux0,
+// aux1); every element w of it (less alpha_r alpha_c when the job carries JOB_TRACE_ALPHA)
+// is weighted with the kernel value and its derivative with respect to log l at the tile
+// pair's u = r^2 / (2 l^2), and the workgroup writes the sums (sum w dk/dlog l, sum w k,
+// sum over the diagonal of w) to partial[blockIdx.x][0..2].  A diagonal tile pair
+// (JOB_LOWER_ONLY) runs the macro tiles on and below its diagonal; its strictly-lower
+// entries count twice, as do all entries of an off-diagonal pair.  Skipped macro tiles
+// write zeros.
+template <int NPROD>
+__global__ __launch_bounds__(BT_THREADS, 1)
+void gemm_bf16x_trace_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs,
+                                  TraceArgs ta) {
+  __shared__ __align__(16) bfraw smem[T256<NPROD>::SMEM];
+  __shared__ double red[3][BT_THREADS / 64];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  GemmJob job;
+  int m0, n0;
+  t256_locate(jobs, njobs, bid, job, m0, n0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+  const int frow = lane & 31, fk = (lane >> 5) * 8;
+  double s_l = 0.0, s_nu = 0.0, s_s = 0.0;
+  if (!((job.flags & JOB_LOWER_ONLY) && (m0 + BT_M - 1 < n0))) {
+    v16f acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    t256_mainloop<NPROD>(job, segs, m0, n0, smem, acc, tid, wm, wn, frow, fk);
+    double ell, nu, s2;
+    resolve_hyper(ta.h, ell, nu, s2);
+    const int64_t ti = job.aux0, tj = job.aux1;
+    const bool diag_tile = ti == tj;
+    const bool with_alpha = job.flags & JOB_TRACE_ALPHA;
+    const double* __restrict__ U = ta.u + (ti * (ti + 1) / 2 + tj) * ta.b * ta.b;
+    if (ta.h.kernel == KERNEL_SE) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = m0 + wm + i * 32 + t256_row(lane, r);
+            const int col = n0 + wn + j * 32 + (lane & 31);
+            const double wt = !diag_tile || row > col ? 2.0 : (row == col ? 1.0 : 0.0);
+            if (wt != 0.0) {
+              const double u = U[(int64_t)row * ta.b + col];
+              double w = (double)acc[i][j][r];
+              if (with_alpha) w -= ta.alpha[ti * ta.b + row] * ta.alpha[tj * ta.b + col];
+              const double kf = nu * exp(-u);
+              s_l = fma(wt * w * kf, 2.0 * u, s_l);
+              s_nu = fma(wt * w, kf, s_nu);
+              if (diag_tile && row == col) s_s += w;
+            }
+          }
+    } else {
+      // The Matern weights are too long a body to unroll 128 times: each lane parks 32 of
+      // its accumulators at a time in its own LDS slots (free once every wave has left the
+      // main loop) and walks them in a loop.
+      __syncthreads();
+      float* const stage = reinterpret_cast<float*>(smem) + wave * 32 * 64;
+      const int kern = ta.h.kernel;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) stage[(j * 16 + r) * 64 + lane] = acc[i][j][r];
+        for (int q = 0; q < 32; ++q) {
+          const int row = m0 + wm + i * 32 + t256_row(lane, q & 15);
+          const int col = n0 + wn + (q >> 4) * 32 + (lane & 31);
+          const double wt = !diag_tile || row > col ? 2.0 : (row == col ? 1.0 : 0.0);
+          if (wt != 0.0) {
+            const double u = U[(int64_t)row * ta.b + col];
+            double w = (double)stage[q * 64 + lane];
+            if (with_alpha) w -= ta.alpha[ti * ta.b + row] * ta.alpha[tj * ta.b + col];
+            double kf, dl;
+            matern_and_dlogl(kern, u, nu, kf, dl);
+            s_l = fma(wt * w, dl, s_l);
+            s_nu = fma(wt * w, kf, s_nu);
+            if (diag_tile && row == col) s_s += w;
+          }
+        }
+      }
+    }
+  }
+  // fixed-order reduction: butterfly within each wave, then the eight wave sums in order
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s_l += __shfl_xor(s_l, o);
+    s_nu += __shfl_xor(s_nu, o);
+    s_s += __shfl_xor(s_s, o);
+  }
+  if (lane == 0) {
+    red[0][wave] = s_l;
+    red[1][wave] = s_nu;
+    red[2][wave] = s_s;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < BT_THREADS / 64; ++q) t += red[tid][q];
+    ta.partial[(int64_t)blockIdx.x * 3 + tid] = t;
+  }
+}
+
+// Split-bfloat16 planes of up to 32 float32 b x b row-major tiles given by address (or of
+// their transposes, TRANS; 16-byte aligned), tile t written at out + t b^2 of each plane
+// (plane stride pstride elements) in the tiled layout above.  Workgroup (x, t): the 256 x 16 block x of
+// output tile t, one thread per output row (reading 16 elements of a source row, or of a
+// source column: consecutive threads read consecutive addresses), 32 bytes written per
+// plane.  lo is written when np == 3.
+struct TileList {
+  const float* p[32];
+};
+template <bool TRANS>
+__global__ __launch_bounds__(256)
+void split_bf16_tiles_kernel(TileList list, int64_t b, bfraw* __restrict__ out, int64_t pstride, int np) {
+  const int64_t t = blockIdx.y, kc = b / BT_K;
+  const int64_t rb = blockIdx.x / kc, kb = blockIdx.x % kc;
+  const int64_t r = rb * BT_M + threadIdx.x;   // row of the output tile
+  const float* __restrict__ src = list.p[t];
+  float x[16];
+  if (TRANS) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = src[(kb * BT_K + e) * b + r];
+  } else {
+    const float4* q = (const float4*)(src + r * b + kb * BT_K);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float4 f = q[e];
+      x[4 * e] = f.x;
+      x[4 * e + 1] = f.y;
+      x[4 * e + 2] = f.z;
+      x[4 * e + 3] = f.w;
+    }
+  }
+  unsigned hw[8], mw[8], lw[8];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const float v = x[e];
+    const bfraw h = bf16_rne_bits(v);
+    const float r1 = v - bf16_to_float(h);
+    const bfraw m = bf16_rne_bits(r1);
+    const bfraw l = bf16_rne_bits(r1 - bf16_to_float(m));
+    if (e & 1) {
+      hw[e >> 1] |= (unsigned)h << 16;
+      mw[e >> 1] |= (unsigned)m << 16;
+      lw[e >> 1] |= (unsigned)l << 16;
+    } else {
+      hw[e >> 1] = h;
+      mw[e >> 1] = m;
+      lw[e >> 1] = l;
+    }
+  }
+  const int64_t o = t * b * b + blockIdx.x * 4096 + (int64_t)threadIdx.x * 16;
+  u32x4* dh = (u32x4*)(out + o);
+  u32x4* dm = (u32x4*)(out + pstride + o);
+  dh[0] = u32x4{hw[0], hw[1], hw[2], hw[3]};
+  dh[1] = u32x4{hw[4], hw[5], hw[6], hw[7]};
+  dm[0] = u32x4{mw[0], mw[1], mw[2], mw[3]};
+  dm[1] = u32x4{mw[4], mw[5], mw[6], mw[7]};
+  if (np == 3) {
+    u32x4* dl = (u32x4*)(out + 2 * pstride + o);
+    dl[0] = u32x4{lw[0], lw[1], lw[2], lw[3]};
+    dl[1] = u32x4{lw[4], lw[5], lw[6], lw[7]};
+  }
+}
+
 hipError_t launch_gemm_bf16_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
                                  hipStream_t st) {
   if (nwg <= 0 || njobs <= 0) return hipSuccess;
@@ -456,6 +669,49 @@ hipError_t launch_gemm_bf16_t256(int nprod, const GemmJob* jobs, const GemmSeg* 
   else
     hipLaunchKernelGGL(gemm_bf16x_t256_kernel<3>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs);
   return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16_trtri_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                                       hipStream_t st) {
+  if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (nprod == 6)
+    hipLaunchKernelGGL(gemm_bf16x_trtri_t256_kernel<6>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs);
+  else
+    hipLaunchKernelGGL(gemm_bf16x_trtri_t256_kernel<3>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16_trace_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                                       const TraceArgs& ta, hipStream_t st) {
+  if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (nprod == 6)
+    hipLaunchKernelGGL(gemm_bf16x_trace_t256_kernel<6>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs, ta);
+  else
+    hipLaunchKernelGGL(gemm_bf16x_trace_t256_kernel<3>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs, ta);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_bf16_tiles(const float* const* tiles, int64_t ntiles, int64_t b, bool trans, void* out,
+                                   int64_t pstride, int np, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (b % BT_M != 0 || (np != 2 && np != 3) || (((uintptr_t)out) & 15) != 0 || pstride % 8 != 0)
+    return hipErrorInvalidValue;
+  for (int64_t t = 0; t < ntiles; ++t)
+    if (((uintptr_t)tiles[t]) & 15) return hipErrorInvalidValue;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += 32) {
+    const int64_t nt = ntiles - t0 < 32 ? ntiles - t0 : 32;
+    TileList list{};
+    for (int64_t t = 0; t < nt; ++t) list.p[t] = tiles[t0 + t];
+    bfraw* o = (bfraw*)out + t0 * b * b;
+    const dim3 grid((unsigned)((b / BT_M) * (b / BT_K)), (unsigned)nt);
+    if (trans)
+      hipLaunchKernelGGL(split_bf16_tiles_kernel<true>, grid, dim3(256), 0, st, list, b, o, pstride, np);
+    else
+      hipLaunchKernelGGL(split_bf16_tiles_kernel<false>, grid, dim3(256), 0, st, list, b, o, pstride, np);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_split_bf16x3_tiled(const float* x, int64_t count, int64_t b, void* hi, void* mid, void* lo,

@@ -24,7 +24,8 @@ struct TimingLog {
     hipEvent_t a, b;
     double flops;
     int kind;   // timing kind: 0/1 float64/float32 update, 2/3 bf16x3/bf16x6 update,
-                // 4/5 float64/float32 inversion step, 6/7 float64/float32 gradient trace
+                // 4/5 float64/float32 inversion step, 6/7 float64/float32 gradient trace,
+                // 8/9 bf16x3/bf16x6 inversion step, 10/11 bf16x3/bf16x6 gradient trace
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -192,7 +193,7 @@ struct Program {
     if (alog && nj > 0) log_gemm(nj);
     if (dagr) {
       if (nj == 0) return;
-      if (f32 || kind == GEMM_KIND_TRACE || gemm_kind_macro(kind) != GEMM_BM || kind == GEMM_KIND_WIDEN ||
+      if (f32 || gemm_kind_trace(kind) || gemm_kind_macro(kind) != GEMM_BM || kind == GEMM_KIND_WIDEN ||
           gemm_kind_bf16(kind)) {
         dagr->ok = false;   // the task form covers the float64 tile products only
         return;
@@ -212,7 +213,7 @@ struct Program {
     gemm_flops_wg += nwg;
     hipEvent_t ea = nullptr, eb = nullptr;
     bool timed = false;
-    if (kind == GEMM_KIND_UPDATE || gemm_kind_bf16(kind) || kind == GEMM_KIND_TRTRI || kind == GEMM_KIND_TRACE) {
+    if (kind == GEMM_KIND_UPDATE || gemm_kind_bf16(kind) || gemm_kind_trtri(kind) || gemm_kind_trace(kind)) {
       std::lock_guard<std::mutex> lk(g_timing.mu);
       if (g_timing.on) {
         ea = g_timing.get();
@@ -238,7 +239,7 @@ struct Program {
         }
       }
     }
-    if (kind == GEMM_KIND_TRACE && (!trace || trace_wg + nwg > trace_cap)) {
+    if (gemm_kind_trace(kind) && (!trace || trace_wg + nwg > trace_cap)) {
       err = hipErrorInvalidValue;
       return;
     }
@@ -246,10 +247,11 @@ struct Program {
     const int bk = 16;   // chunk depth of the main loop (both product types)
     const int spec = gemm_kind_bf16(kind) ? -1 : gemm_launch_spec(jobs.data() + job0, nj, segs.data(), esize, bk);
     if (timed) (void)hipEventRecord(ea, sx);
-    if (kind == GEMM_KIND_TRACE) {
+    if (gemm_kind_trace(kind)) {
       TraceArgs ta = *trace;
       ta.partial += 3 * trace_wg;
-      err = launch_gemm_trace(f32, djobs + job0, dsegs, nj, nwg, spec, ta, sx);
+      err = gemm_kind_bf16(kind) ? launch_gemm_bf16_trace_t256(gemm_kind_nprod(kind), djobs + job0, dsegs, nj, nwg, ta, sx)
+                                 : launch_gemm_trace(f32, djobs + job0, dsegs, nj, nwg, spec, ta, sx);
       trace_wg += nwg;
     } else {
       err = launch_gemm(f32, djobs + job0, dsegs, nj, nwg, kind, spec, sx);
@@ -258,7 +260,8 @@ struct Program {
       (void)hipEventRecord(eb, sx);
       std::lock_guard<std::mutex> lk(g_timing.mu);
       int tk = f32 ? 1 : 0;
-      if (gemm_kind_bf16(kind)) tk = gemm_kind_nprod(kind) == 6 ? 3 : 2;
+      const int six = gemm_kind_nprod(kind) == 6 ? 1 : 0;
+      if (gemm_kind_bf16(kind)) tk = gemm_kind_trtri(kind) ? 8 + six : (gemm_kind_trace(kind) ? 10 + six : 2 + six);
       else if (kind == GEMM_KIND_TRTRI) tk = f32 ? 5 : 4;
       else if (kind == GEMM_KIND_TRACE) tk = f32 ? 7 : 6;
       g_timing.recs.push_back({ea, eb, kind_flops, tk});

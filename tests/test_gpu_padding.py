@@ -94,25 +94,36 @@ def test_padded_matern_gradient(lib, kernel):
     np.testing.assert_allclose(grad.cpu().numpy(), go, rtol=1e-9, atol=1e-9 * np.max(np.abs(go)))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
-def test_padded_mixed_precision(lib, prec):
+# prec: (factor max-abs / max|L|, variance, gradient) bounds of the mixed modes (the
+# three-product split carries about 16 significant bits per product)
+MIXED_BOUNDS = {"fp32": (1e-4, 1e-4, 1e-3), "bf16x6": (1e-4, 1e-4, 1e-3), "bf16x3": (1e-3, 1e-3, 1e-2)}
+
+
+@pytest.mark.parametrize("prec,tile", [("fp32", 192), ("bf16x6", 192), ("bf16x6", 256), ("bf16x3", 256)])
+def test_padded_mixed_precision(lib, prec, tile):
+    """Tile 192 (T = 6, last tile 40 real rows) runs the float32 products of the gradient in
+    every mixed mode; tile 256 (T = 4, last tile 232 real rows) runs the split modes'
+    gradient from bfloat16 planes."""
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=1000, n_test=100, D=8, seed=3))
     h = Hyper(math.sqrt(8), 1.0, 0.01)
     L, a, f = oracle.fit(ds.Z, ds.y, h)
-    tile = 192                                   # T = 6, last tile 40 real rows
-    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, prec=prec, sweeps=3, m=100)
+    f_tol, v_tol, g_tol = MIXED_BOUNDS[prec]
+    T = -(-1000 // tile)
+    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, prec=prec, sweeps=6 if prec == "bf16x3" else 3, m=100)
     Lg = tiles_to_dense_lower(g["K"].cpu().numpy(), 1000, tile, 4)
-    assert np.max(np.abs(Lg[:1000, :1000] - L)) / np.max(np.abs(L)) < 1e-4
-    assert np.all(Lg[1000:, :1000] == 0.0) and np.array_equal(Lg[1000:, 1000:], np.eye(152))
+    assert np.max(np.abs(Lg[:1000, :1000] - L)) / np.max(np.abs(L)) < f_tol
+    assert np.all(Lg[1000:, :1000] == 0.0) and np.array_equal(Lg[1000:, 1000:], np.eye(T * tile - 1000))
     assert abs(g["nlml"] - f) / abs(f) < 1e-6
     assert_close(g["alpha"].cpu().numpy(), a, 1e-6)
     mean, var = _gpu_predict(lib, g, ds.Zs, h)
     assert_close(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a), 1e-6)
-    assert_close(var, oracle.predict_var(ds.Z, ds.Zs, h, L), 1e-4)
+    assert_close(var, oracle.predict_var(ds.Z, ds.Zs, h, L), v_tol)
     go = oracle.nlml_grad(ds.Z, h, L, a)
     grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
     lib.gpr_nlml_grad(g["Z"], 1000, 8, h, g["K"], tile, prec, g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
-    np.testing.assert_allclose(grad.cpu().numpy(), go, rtol=1e-3, atol=1e-3 * np.max(np.abs(go)))
+    ge = grad.cpu().numpy()
+    print(f"[padding] {prec} tile {tile}: gradient {ge} oracle {go}", flush=True)
+    np.testing.assert_allclose(ge, go, rtol=g_tol, atol=g_tol * np.max(np.abs(go)))
 
 
 def test_padded_optimize_matches_oracle_adam(lib):
