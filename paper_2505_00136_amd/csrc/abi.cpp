@@ -830,8 +830,19 @@ struct VarWs {
   void* rowt;      // block row i of L with each tile transposed: (T-1) b x b tiles
   float* w32;      // T b x b float32 copies of the diagonal-tile inverses (mixed)
   double* partial; // column sums of squares
+  // split modes (tiles and m multiples of 256): bfloat16 planes of the products' operands,
+  // plane strides *s elements: V_j^T for every block j (m x b each), block row i of L and
+  // W_ii (T tiles), the right-hand side of W_ii (m x b)
+  uint16_t *pv, *pl, *pt;
+  int64_t pvs, pls, pts;
   void* arena;
 };
+
+// The split modes run the variance's forward substitution from bfloat16 planes when the
+// tiles and the number of test points suit the 256 x 256 kernels, float32 otherwise.
+bool var_split(const TileLayout& L, int64_t m, int prec) {
+  return is_bf16(prec) && bf16_tiled(L) && m > 0 && m % 256 == 0;
+}
 
 void describe_var(Program& P, const TileLayout& L, const void* Kc, int64_t m, int prec, const VarWs& w) {
   const int64_t b = L.b, T = L.T;
@@ -863,6 +874,58 @@ void describe_var(Program& P, const TileLayout& L, const void* Kc, int64_t m, in
   }
 }
 
+// describe_var from split-bfloat16 planes (var_split): block i splits L_ij (j < i) as
+// stored, then tmp = B_i - sum_j L_ij V_j against the planes of V_j^T kept from earlier
+// blocks; then it splits W_ii and the right-hand side transposed, V_i = W_ii tmp (W_ii in
+// full, with its zeros), and keeps the planes of V_i^T for the later blocks.  V stays
+// float32 for the float64 sums of squares and the full covariance.
+void describe_var_split(Program& P, const TileLayout& L, const void* Kc, int64_t m, int prec, const VarWs& w) {
+  const int64_t b = L.b, T = L.T, bb = b * b;
+  const int np = prec == GPR_BF16X6 ? 3 : 2;
+  const int kind = prec == GPR_BF16X6 ? GEMM_KIND_BF16X6_SOLVE_T256 : GEMM_KIND_BF16X3_SOLVE_T256;
+  void* K = const_cast<void*>(Kc);
+  auto split = [&](std::vector<const float*> src, int64_t rows, int64_t ld, bool trans, uint16_t* out, int64_t ps) {
+    P.kernel([=](hipStream_t s) {
+      return launch_split_bf16_tiles(src.data(), (int64_t)src.size(), rows, b, ld, trans, out, ps, np, s);
+    });
+  };
+  float* const V = (float*)w.V;
+  float* const tmp = (float*)w.tmp;
+  uint16_t* const wslot = w.pl + (T - 1) * bb;   // W_ii (block row i of L uses slots 0 .. i-1)
+  for (int64_t i = 0; i < T; ++i) {
+    float* Vi = V + i * b * m;
+    const float* rhs = Vi;
+    if (i > 0) {
+      std::vector<const float*> row(i);
+      for (int64_t j = 0; j < i; ++j) row[j] = (const float*)L.off(K, i, j);
+      split(row, b, b, false, w.pl, w.pls);
+      P.gemm_begin(1, kind);
+      P.job(tmp, m, Vi, m, b, m, -1.0, 1.0, JOB_C_F32);
+      for (int64_t j = 0; j < i; ++j) {
+        P.seg(w.pl + j * bb, b, MODE_KC, w.pv + j * b * m, b, MODE_KC, b, 0);
+        P.segs.back().pstrideA = w.pls;
+        P.segs.back().pstrideB = w.pvs;
+      }
+      P.gemm_end();
+      rhs = tmp;
+    }
+    split({rhs}, m, m, true, w.pt, w.pts);
+    split({w.w32 + i * bb}, b, b, false, wslot, w.pls);
+    P.gemm_begin(1, kind);
+    P.job(Vi, m, nullptr, 0, b, m, 1.0, 0.0, JOB_C_F32);
+    P.seg(wslot, b, MODE_KC, w.pt, b, MODE_KC, b, 0);
+    P.segs.back().pstrideA = w.pls;
+    P.segs.back().pstrideB = w.pts;
+    P.gemm_end();
+    if (i < T - 1) split({Vi}, m, m, true, w.pv + i * b * m, w.pvs);
+  }
+}
+
+void describe_variance(Program& P, const TileLayout& L, const void* Kc, int64_t m, int prec, const VarWs& w) {
+  if (var_split(L, m, prec)) describe_var_split(P, L, Kc, m, prec, w);
+  else describe_var(P, L, Kc, m, prec, w);
+}
+
 // Sigma = K_{Zs,Zs} - V^T V: float64 products and accumulation in every precision (the
 // mixed modes store V in float32 and widen each product to float64).
 void describe_fullcov(Program& P, const TileLayout& L, int64_t m, int prec, const VarWs& w, double* out) {
@@ -878,9 +941,19 @@ VarWs carve_var(Carve& c, const TileLayout& L, int64_t m, int prec) {
   const int es = is_mixed(prec) ? 4 : 8;
   w.V = c.take<char>((size_t)L.npad() * m * es);
   w.tmp = c.take<char>((size_t)L.b * m * es);
-  w.rowt = c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * es);
+  const bool split = var_split(L, m, prec);
+  w.rowt = split ? nullptr : c.take<char>((size_t)(L.T > 1 ? L.T - 1 : 0) * L.b * L.b * es);
   w.w32 = is_mixed(prec) ? c.take<float>((size_t)L.T * L.b * L.b) : nullptr;
   w.partial = c.take<double>((size_t)ceil_div(std::max<int64_t>(L.n, 1), kRowsPerChunk) * m);
+  if (split) {
+    const int np = prec == GPR_BF16X6 ? 3 : 2;
+    w.pvs = L.npad() * m;
+    w.pls = L.T * L.b * L.b;
+    w.pts = m * L.b;
+    w.pv = c.take<uint16_t>((size_t)np * w.pvs);
+    w.pl = c.take<uint16_t>((size_t)np * w.pls);
+    w.pt = c.take<uint16_t>((size_t)np * w.pts);
+  }
   w.arena = c.take<char>(0);
   return w;
 }
@@ -1009,7 +1082,7 @@ void describe_trtri_split(Program& P, const TileLayout& L, void* K, int prec, co
   uint16_t* const pb = w.pb;
   auto split = [&](std::vector<const float*> src, bool trans, uint16_t* out) {
     P.kernel([=](hipStream_t s) {
-      return launch_split_bf16_tiles(src.data(), (int64_t)src.size(), b, trans, out, ps, np, s);
+      return launch_split_bf16_tiles(src.data(), (int64_t)src.size(), b, b, b, trans, out, ps, np, s);
     });
   };
   auto seg = [&](const uint16_t* A, const uint16_t* B) {
@@ -1067,7 +1140,7 @@ void describe_lauum_trace_split(Program& P, const TileLayout& L, void* K, int pr
     for (int64_t i = 0; i < k; ++i) x[i] = (const float*)L.off(K, k, i);
     x[k] = w.w32 + k * bb;
     P.kernel([=](hipStream_t s) {
-      return launch_split_bf16_tiles(x.data(), (int64_t)x.size(), b, true, pb, ps, np, s);
+      return launch_split_bf16_tiles(x.data(), (int64_t)x.size(), b, b, b, true, pb, ps, np, s);
     });
     const double kd = (double)k;
     P.gemm_begin(1, kind, kd * (kd - 1.0) / 2.0 * full + 2.0 * kd * half + tri3);
@@ -1159,7 +1232,7 @@ size_t var_ws_bytes(const TileLayout& L, int64_t m, int prec, bool full) {
   Carve c(kSymWs);
   VarWs w = carve_var(c, L, m, prec);
   Program P;
-  describe_var(P, L, kSymK, m, prec, w);
+  describe_variance(P, L, kSymK, m, prec, w);
   if (full) describe_fullcov(P, L, m, prec, w, (double*)kSymOut);
   return c.off + arena_bytes_of(P);
 }
@@ -1212,7 +1285,7 @@ size_t table_bytes(const TileLayout& L, int64_t m, int prec) {
     Carve c(kSymWs);
     VarWs w = carve_var(c, L, m, prec);
     Program P;
-    describe_var(P, L, kSymK, m, prec, w);
+    describe_variance(P, L, kSymK, m, prec, w);
     describe_fullcov(P, L, m, prec, w, (double*)kSymOut);
     t = std::max(t, arena_bytes_of(P));
   }
@@ -1512,7 +1585,7 @@ GPR_API int gpr_predict_var(const double* Z, int64_t n, const double* Zs, int64_
   if (full_cov) HIPCHK(launch_assemble_dense(Zs, m, Zs, m, d, ha, add_noise, out, m, 0, st));
   rc = run_program(
       [&](Program& P) {
-        describe_var(P, L, L_tiles, m, prec, w);
+        describe_variance(P, L, L_tiles, m, prec, w);
         if (full_cov) describe_fullcov(P, L, m, prec, w, out);
       },
       w.arena, ws_bytes - c.off, st);

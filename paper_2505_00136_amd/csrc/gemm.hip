@@ -186,6 +186,7 @@ hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, i
     return launch_gemm_bf16_t256(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
   if (kind == GEMM_KIND_BF16X3_TRTRI_T256 || kind == GEMM_KIND_BF16X6_TRTRI_T256)
     return launch_gemm_bf16_trtri_t256(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
+  if (gemm_kind_solve(kind)) return launch_gemm_bf16_solve_t256(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
   if (kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6)
     return launch_gemm_bf16(gemm_kind_nprod(kind), jobs, segs, njobs, nwg, st);
   if (gemm_kind_trace(kind)) return hipErrorInvalidValue;   // launched by launch_gemm_trace

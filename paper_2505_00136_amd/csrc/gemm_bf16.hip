@@ -598,28 +598,31 @@ void gemm_bf16x_trace_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSe
   }
 }
 
-// Split-bfloat16 planes of up to 32 float32 b x b row-major tiles given by address (or of
-// their transposes, TRANS; 16-byte aligned), tile t written at out + t b^2 of each plane
-// (plane stride pstride elements) in the tiled layout above.  Workgroup (x, t): the 256 x 16 block x of
-// output tile t, one thread per output row (reading 16 elements of a source row, or of a
-// source column: consecutive threads read consecutive addresses), 32 bytes written per
-// plane.  lo is written when np == 3.
+// Split-bfloat16 planes of up to 32 float32 blocks given by address, each a rows x kd
+// operand (rows and kd multiples of 256 and 16) read from a row-major source with
+// leading dimension ld -- element (r, c) at src[r ld + c], or at src[c ld + r] (TRANS: the
+// operand is the transpose of a kd x rows source block) -- written in the tiled layout
+// above: block t at out + t rows kd of each plane (plane stride pstride elements).
+// Workgroup (x, t): the 256 x 16 chunk x of block t, one thread per operand row (reading
+// 16 elements of a source row, or of a source column: consecutive threads read
+// consecutive addresses), 32 bytes written per plane.  lo is written when np == 3.
 struct TileList {
   const float* p[32];
 };
 template <bool TRANS>
 __global__ __launch_bounds__(256)
-void split_bf16_tiles_kernel(TileList list, int64_t b, bfraw* __restrict__ out, int64_t pstride, int np) {
-  const int64_t t = blockIdx.y, kc = b / BT_K;
+void split_bf16_tiles_kernel(TileList list, int64_t rows, int64_t kd, int64_t ld, bfraw* __restrict__ out,
+                             int64_t pstride, int np) {
+  const int64_t t = blockIdx.y, kc = kd / BT_K;
   const int64_t rb = blockIdx.x / kc, kb = blockIdx.x % kc;
-  const int64_t r = rb * BT_M + threadIdx.x;   // row of the output tile
+  const int64_t r = rb * BT_M + threadIdx.x;   // operand row
   const float* __restrict__ src = list.p[t];
   float x[16];
   if (TRANS) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = src[(kb * BT_K + e) * b + r];
+    for (int e = 0; e < 16; ++e) x[e] = src[(kb * BT_K + e) * ld + r];
   } else {
-    const float4* q = (const float4*)(src + r * b + kb * BT_K);
+    const float4* q = (const float4*)(src + r * ld + kb * BT_K);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const float4 f = q[e];
@@ -647,7 +650,7 @@ void split_bf16_tiles_kernel(TileList list, int64_t b, bfraw* __restrict__ out, 
       lw[e >> 1] = l;
     }
   }
-  const int64_t o = t * b * b + blockIdx.x * 4096 + (int64_t)threadIdx.x * 16;
+  const int64_t o = t * rows * kd + blockIdx.x * 4096 + (int64_t)threadIdx.x * 16;
   u32x4* dh = (u32x4*)(out + o);
   u32x4* dm = (u32x4*)(out + pstride + o);
   dh[0] = u32x4{hw[0], hw[1], hw[2], hw[3]};
@@ -659,6 +662,15 @@ void split_bf16_tiles_kernel(TileList list, int64_t b, bfraw* __restrict__ out, 
     dl[0] = u32x4{lw[0], lw[1], lw[2], lw[3]};
     dl[1] = u32x4{lw[4], lw[5], lw[6], lw[7]};
   }
+}
+
+// The forward substitution of the posterior variance (V_i = W_ii (B_i - sum_j L_ij V_j))
+// from split-bfloat16 planes (same code as the update, its own symbol).
+template <int NPROD>
+__global__ __launch_bounds__(BT_THREADS, 1)
+void gemm_bf16x_solve_t256_kernel(const GemmJob* __restrict__ jobs, const GemmSeg* __restrict__ segs, int njobs) {
+  __shared__ __align__(16) bfraw smem[T256<NPROD>::SMEM];
+  t256_body<NPROD>(jobs, segs, njobs, smem);
 }
 
 hipError_t launch_gemm_bf16_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
@@ -691,23 +703,34 @@ hipError_t launch_gemm_bf16_trace_t256(int nprod, const GemmJob* jobs, const Gem
   return hipGetLastError();
 }
 
-hipError_t launch_split_bf16_tiles(const float* const* tiles, int64_t ntiles, int64_t b, bool trans, void* out,
-                                   int64_t pstride, int np, hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
-  if (b % BT_M != 0 || (np != 2 && np != 3) || (((uintptr_t)out) & 15) != 0 || pstride % 8 != 0)
+hipError_t launch_gemm_bf16_solve_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                                       hipStream_t st) {
+  if (nwg <= 0 || njobs <= 0) return hipSuccess;
+  if (nprod == 6)
+    hipLaunchKernelGGL(gemm_bf16x_solve_t256_kernel<6>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs);
+  else
+    hipLaunchKernelGGL(gemm_bf16x_solve_t256_kernel<3>, dim3(nwg), dim3(BT_THREADS), 0, st, jobs, segs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_bf16_tiles(const float* const* blocks, int64_t nblocks, int64_t rows, int64_t kd, int64_t ld,
+                                   bool trans, void* out, int64_t pstride, int np, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (rows % BT_M != 0 || kd % BT_K != 0 || rows <= 0 || kd <= 0 || (np != 2 && np != 3) ||
+      (((uintptr_t)out) & 15) != 0 || pstride % 8 != 0 || (!trans && ld % 4 != 0) || ld < (trans ? rows : kd))
     return hipErrorInvalidValue;
-  for (int64_t t = 0; t < ntiles; ++t)
-    if (((uintptr_t)tiles[t]) & 15) return hipErrorInvalidValue;
-  for (int64_t t0 = 0; t0 < ntiles; t0 += 32) {
-    const int64_t nt = ntiles - t0 < 32 ? ntiles - t0 : 32;
+  for (int64_t t = 0; t < nblocks; ++t)
+    if (((uintptr_t)blocks[t]) & 15) return hipErrorInvalidValue;
+  for (int64_t t0 = 0; t0 < nblocks; t0 += 32) {
+    const int64_t nt = nblocks - t0 < 32 ? nblocks - t0 : 32;
     TileList list{};
-    for (int64_t t = 0; t < nt; ++t) list.p[t] = tiles[t0 + t];
-    bfraw* o = (bfraw*)out + t0 * b * b;
-    const dim3 grid((unsigned)((b / BT_M) * (b / BT_K)), (unsigned)nt);
+    for (int64_t t = 0; t < nt; ++t) list.p[t] = blocks[t0 + t];
+    bfraw* o = (bfraw*)out + t0 * rows * kd;
+    const dim3 grid((unsigned)((rows / BT_M) * (kd / BT_K)), (unsigned)nt);
     if (trans)
-      hipLaunchKernelGGL(split_bf16_tiles_kernel<true>, grid, dim3(256), 0, st, list, b, o, pstride, np);
+      hipLaunchKernelGGL(split_bf16_tiles_kernel<true>, grid, dim3(256), 0, st, list, rows, kd, ld, o, pstride, np);
     else
-      hipLaunchKernelGGL(split_bf16_tiles_kernel<false>, grid, dim3(256), 0, st, list, b, o, pstride, np);
+      hipLaunchKernelGGL(split_bf16_tiles_kernel<false>, grid, dim3(256), 0, st, list, rows, kd, ld, o, pstride, np);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -19,15 +19,20 @@ enum { GEMM_KIND_GENERIC = 0, GEMM_KIND_UPDATE = 1, GEMM_KIND_BF16X3 = 2, GEMM_K
        // the gradient's inversion steps and fused trace products from split-bfloat16 planes
        // on 256 x 256 macro tiles (own kernel symbols)
        GEMM_KIND_BF16X3_TRTRI_T256 = 9, GEMM_KIND_BF16X6_TRTRI_T256 = 10,
-       GEMM_KIND_BF16X3_TRACE_T256 = 11, GEMM_KIND_BF16X6_TRACE_T256 = 12 };
+       GEMM_KIND_BF16X3_TRACE_T256 = 11, GEMM_KIND_BF16X6_TRACE_T256 = 12,
+       // the variance's forward substitution (own kernel symbols, not timed)
+       GEMM_KIND_BF16X3_SOLVE_T256 = 13, GEMM_KIND_BF16X6_SOLVE_T256 = 14 };
 inline bool gemm_kind_bf16(int kind) {
-  return kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6 || (kind >= GEMM_KIND_BF16X3_T256 && kind <= 12);
+  return kind == GEMM_KIND_BF16X3 || kind == GEMM_KIND_BF16X6 || (kind >= GEMM_KIND_BF16X3_T256 && kind <= 14);
 }
 inline int gemm_kind_nprod(int kind) {
   return (kind == GEMM_KIND_BF16X6 || kind == GEMM_KIND_BF16X6_T256 || kind == GEMM_KIND_BF16X6_TRTRI_T256 ||
-          kind == GEMM_KIND_BF16X6_TRACE_T256)
+          kind == GEMM_KIND_BF16X6_TRACE_T256 || kind == GEMM_KIND_BF16X6_SOLVE_T256)
              ? 6
              : 3;
+}
+inline bool gemm_kind_solve(int kind) {
+  return kind == GEMM_KIND_BF16X3_SOLVE_T256 || kind == GEMM_KIND_BF16X6_SOLVE_T256;
 }
 inline bool gemm_kind_trtri(int kind) {
   return kind == GEMM_KIND_TRTRI || kind == GEMM_KIND_BF16X3_TRTRI_T256 || kind == GEMM_KIND_BF16X6_TRTRI_T256;
@@ -36,7 +41,7 @@ inline bool gemm_kind_trace(int kind) {
   return kind == GEMM_KIND_TRACE || kind == GEMM_KIND_BF16X3_TRACE_T256 || kind == GEMM_KIND_BF16X6_TRACE_T256;
 }
 // macro tile edge of a launch of this kind (the workgroup count of each job follows from it)
-inline int gemm_kind_macro(int kind) { return kind >= GEMM_KIND_BF16X3_T256 && kind <= 12 ? 256 : GEMM_BM; }
+inline int gemm_kind_macro(int kind) { return kind >= GEMM_KIND_BF16X3_T256 && kind <= 14 ? 256 : GEMM_BM; }
 // spec: main-loop specialisation from gemm_launch_spec (host tables of the launch)
 hipError_t launch_gemm(int prec_f32, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg, int kind, int spec,
                        hipStream_t st);
@@ -65,11 +70,16 @@ hipError_t launch_gemm_bf16_trtri_t256(int nprod, const GemmJob* jobs, const Gem
                                        hipStream_t st);
 hipError_t launch_gemm_bf16_trace_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
                                        const TraceArgs& ta, hipStream_t st);
-// planes (2 or 3) of ntiles float32 b x b row-major tiles at the given (16-byte aligned)
-// addresses, or of their transposes, in the tiled layout; tile t at out + t b^2 of each
-// plane, plane stride pstride elements (a multiple of 8)
-hipError_t launch_split_bf16_tiles(const float* const* tiles, int64_t ntiles, int64_t b, bool trans, void* out,
-                                   int64_t pstride, int np, hipStream_t st);
+// the variance's forward substitution on 256 x 256 macro tiles
+hipError_t launch_gemm_bf16_solve_t256(int nprod, const GemmJob* jobs, const GemmSeg* segs, int njobs, int nwg,
+                                       hipStream_t st);
+// planes (2 or 3) of nblocks rows x kd operands (rows % 256 == 0, kd % 16 == 0) read from
+// float32 row-major blocks at the given (16-byte aligned) addresses with leading dimension
+// ld, as stored or transposed (trans: operand element (r, c) is source element (c, r)), in
+// the tiled layout; block t at out + t rows kd of each plane, plane stride pstride
+// elements (a multiple of 8)
+hipError_t launch_split_bf16_tiles(const float* const* blocks, int64_t nblocks, int64_t rows, int64_t kd, int64_t ld,
+                                   bool trans, void* out, int64_t pstride, int np, hipStream_t st);
 
 // potrf_block.hip: Cholesky + inverse of one jb x jb (jb <= 64) diagonal block by one workgroup
 hipError_t launch_potrf_block(double* A, int64_t lda, double* W, int64_t ldw, int jb, int64_t col_base,

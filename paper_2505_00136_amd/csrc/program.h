@@ -213,7 +213,8 @@ struct Program {
     gemm_flops_wg += nwg;
     hipEvent_t ea = nullptr, eb = nullptr;
     bool timed = false;
-    if (kind == GEMM_KIND_UPDATE || gemm_kind_bf16(kind) || gemm_kind_trtri(kind) || gemm_kind_trace(kind)) {
+    if (kind == GEMM_KIND_UPDATE || (gemm_kind_bf16(kind) && !gemm_kind_solve(kind)) || gemm_kind_trtri(kind) ||
+        gemm_kind_trace(kind)) {
       std::lock_guard<std::mutex> lk(g_timing.mu);
       if (g_timing.on) {
         ea = g_timing.get();

@@ -101,15 +101,15 @@ MIXED_BOUNDS = {"fp32": (1e-4, 1e-4, 1e-3), "bf16x6": (1e-4, 1e-4, 1e-3), "bf16x
 
 @pytest.mark.parametrize("prec,tile", [("fp32", 192), ("bf16x6", 192), ("bf16x6", 256), ("bf16x3", 256)])
 def test_padded_mixed_precision(lib, prec, tile):
-    """Tile 192 (T = 6, last tile 40 real rows) runs the float32 products of the gradient in
-    every mixed mode; tile 256 (T = 4, last tile 232 real rows) runs the split modes'
-    gradient from bfloat16 planes."""
-    ds = datagen.make_dataset(datagen.MSDConfig(n_train=1000, n_test=100, D=8, seed=3))
+    """Tile 192 (T = 6, last tile 40 real rows) runs the float32 products of the gradient and
+    the variance in every mixed mode; tile 256 (T = 4, last tile 232 real rows) runs the
+    split modes' gradient and variance (256 test points) from bfloat16 planes."""
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=1000, n_test=256, D=8, seed=3))
     h = Hyper(math.sqrt(8), 1.0, 0.01)
     L, a, f = oracle.fit(ds.Z, ds.y, h)
     f_tol, v_tol, g_tol = MIXED_BOUNDS[prec]
     T = -(-1000 // tile)
-    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, prec=prec, sweeps=6 if prec == "bf16x3" else 3, m=100)
+    g = _gpu_fit(lib, ds.Z, ds.y, h, tile, prec=prec, sweeps=6 if prec == "bf16x3" else 3, m=256)
     Lg = tiles_to_dense_lower(g["K"].cpu().numpy(), 1000, tile, 4)
     assert np.max(np.abs(Lg[:1000, :1000] - L)) / np.max(np.abs(L)) < f_tol
     assert np.all(Lg[1000:, :1000] == 0.0) and np.array_equal(Lg[1000:, 1000:], np.eye(T * tile - 1000))
