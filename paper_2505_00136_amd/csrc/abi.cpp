@@ -747,7 +747,7 @@ CholWs carve_chol(void* ws, const TileLayout& L, int prec, size_t ws_bytes, bool
 
 // ================================================================ triangular solves
 struct SolveWs {
-  double *r, *z, *t, *partial, *kpart, *res, *dvec;
+  double *r, *z, *t, *partial, *kpart, *kcol, *res, *dvec;
   double* xp;   // padded solution (T b) when the tile does not divide n
 };
 
@@ -764,6 +764,7 @@ SolveWs carve_solve(Carve& c, const TileLayout& L) {
   w.t = c.take<double>(b);
   w.partial = c.take<double>(solve_partial_rows(L) * b);
   w.kpart = c.take<double>((size_t)ceil_div(std::max<int64_t>(n, 1), kColsPerChunk) * n);
+  w.kcol = c.take<double>((size_t)ceil_div(std::max<int64_t>(n, 1), GEMM_BM) * n);
   w.res = c.take<double>(n);
   w.dvec = c.take<double>(n);
   w.xp = npad > n ? c.take<double>(npad) : nullptr;
@@ -814,8 +815,14 @@ int solve_impl(const TileLayout& L, const void* K, const double* Z, int64_t d, H
   const int64_t n = L.n;
   for (int s = 0; s < sweeps; ++s) {
     // r = y - K alpha in float64, K regenerated from Z (matrix-free)
-    HIPCHK(launch_kmatvec_partial(Z, n, Z, n, d, h, alpha, w.kpart, kColsPerChunk, st));
-    HIPCHK(launch_residual_finish(w.kpart, ceil_div(n, kColsPerChunk), n, h, y, alpha, w.res, st));
+    if (h.kernel == KERNEL_SE) {
+      // the symmetry of K halves the pairs
+      HIPCHK(launch_se_kmatvec_gram_sym(Z, n, d, h, alpha, w.kpart, w.kcol, kColsPerChunk, st));
+      HIPCHK(launch_residual_finish_sym(w.kpart, ceil_div(n, kColsPerChunk), w.kcol, n, h, y, alpha, w.res, st));
+    } else {
+      HIPCHK(launch_kmatvec_partial(Z, n, Z, n, d, h, alpha, w.kpart, kColsPerChunk, st));
+      HIPCHK(launch_residual_finish(w.kpart, ceil_div(n, kColsPerChunk), n, h, y, alpha, w.res, st));
+    }
     rc = tri_solve(L, K, w.res, w.dvec, w, st);
     if (rc) return rc;
     HIPCHK(launch_axpy(alpha, w.dvec, 1.0, n, st));

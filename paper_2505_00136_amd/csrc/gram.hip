@@ -108,14 +108,20 @@ GPR_DEV void explicit_r2(const double* __restrict__ A, int64_t rlim, int64_t r0,
 // Grid (ceil(rows / 128), chunks); workgroup (x, y) takes rows 128 x .. and the points of
 // chunk y in blocks of 128.  `same`: A and B are the same points (a pair (i, i) is at
 // distance 0).
-template <int SPEC>
+// SYM (A = B, the refinement's K alpha): K is symmetric, so workgroup (x, y) takes only the
+// blocks of chunk y at or left of the diagonal block x; a block left of it (c0 < r0) also
+// adds its column sums sum_i k(a_i, b_j) v_i, written to colpart[x][j] (each entry by one
+// workgroup; entries of columns in or right of block x are not written).  The sum over
+// i of k_ij v_j then takes partial over the chunks plus colpart[x][i] over x > i / 128.
+template <int SPEC, bool SYM>
 __global__ __launch_bounds__(GrShape::THREADS, 2)
 void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const double* __restrict__ B, int64_t cols,
                             int64_t d, HyperArg h, const double* __restrict__ v, double* __restrict__ partial,
-                            int64_t chunk_cols, int same) {
+                            double* __restrict__ colpart, int64_t chunk_cols, int same) {
   __shared__ __align__(16) char smem[Chunk<double>::SMEM];
   __shared__ double na[GEMM_BM], nb[GEMM_BN];
   __shared__ double red[GR_WN][GEMM_BM];
+  __shared__ double va[SYM ? GEMM_BM : 1], cred[SYM ? 2 : 1][SYM ? GEMM_BN : 1];
   __shared__ double maxna, maxnb;
   __shared__ GemmSeg seg;
   LdsBuf<double> As = reinterpret_cast<LdsBuf<double>>(smem);
@@ -124,12 +130,14 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
   const int wm = GrShape::m0(wave), wn = GrShape::n0(wave);
   const int64_t r0 = (int64_t)blockIdx.x * GEMM_BM;
   const int64_t cbeg = (int64_t)blockIdx.y * chunk_cols;
-  const int64_t cend = cbeg + chunk_cols < cols ? cbeg + chunk_cols : cols;
+  int64_t cend = cbeg + chunk_cols < cols ? cbeg + chunk_cols : cols;
+  if (SYM && cend > r0 + GEMM_BN) cend = r0 + GEMM_BN;   // blocks at or left of the diagonal block
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
   const double g = -0.5 / (ell * ell);
   if (tid == 0) seg = GemmSeg{A, B, d, d, 0, 0, (int32_t)d, MODE_KC, MODE_KC, 0, 0};
   if (tid < GR_WN * GEMM_BM) red[tid / GEMM_BM][tid % GEMM_BM] = 0.0;
+  if (SYM && tid < GEMM_BM) va[tid] = r0 + tid < rows ? v[r0 + tid] : 0.0;
   GemmJob job{};
   job.M = (int32_t)rows;
   job.N = (int32_t)cols;
@@ -164,11 +172,13 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
     } else {
       explicit_r2<GrShape::NJ>(A, rows, r0, B, cend, c0, d, smem, acc, lane, wm, wn);
     }
-    double vj[GrShape::NJ];
+    double vj[GrShape::NJ], cs[GrShape::NJ];
+    const bool colsums = SYM && c0 < r0;   // a block left of the diagonal block
 #pragma unroll
     for (int j = 0; j < GrShape::NJ; ++j) {
       const int64_t col = c0 + wn + j * 16 + (lane & 15);
       vj[j] = col < cend ? v[col] : 0.0;
+      cs[j] = 0.0;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -183,7 +193,11 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
           const int64_t col = c0 + lc;
           double r2 = acc[i][j][r];
           if (same && row == col) r2 = 0.0;
-          if (row < rows && col < cend) s = fma(nu * exp(g * r2), vj[j], s);
+          if (row < rows && col < cend) {
+            const double kv = nu * exp(g * r2);
+            s = fma(kv, vj[j], s);
+            if (colsums) cs[j] = fma(kv, va[lr], cs[j]);
+          }
         }
         // the 16 lanes holding this row (different columns), then one lane per row adds
         // the block's sum to its wave's slot
@@ -193,7 +207,20 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
         s += __shfl_xor(s, 8);
         if ((lane & 15) == 0) red[wave % GR_WN][lr] += s;
       }
-    __syncthreads();   // nb and the LDS operand buffers are rewritten by the next block
+    if (colsums) {
+      // the four lanes holding each column (rows 16 apart), then the two waves of each
+      // column range (rows 0-63 and 64-127) through LDS, in a fixed order
+#pragma unroll
+      for (int j = 0; j < GrShape::NJ; ++j) {
+        cs[j] += __shfl_xor(cs[j], 16);
+        cs[j] += __shfl_xor(cs[j], 32);
+        if (lane < 16) cred[wave / GR_WN][wn + j * 16 + lane] = cs[j];
+      }
+      __syncthreads();
+      if (tid < GEMM_BN && c0 + tid < cend)
+        colpart[(int64_t)blockIdx.x * cols + c0 + tid] = cred[0][tid] + cred[1][tid];
+    }
+    __syncthreads();   // nb, cred and the LDS operand buffers are rewritten by the next block
   }
   if (tid < GEMM_BM) {
     double s = 0.0;
@@ -217,11 +244,27 @@ hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B
   const bool full = rows % GEMM_BM == 0 && cols % GEMM_BN == 0 && d % Chunk<double>::BK == 0 &&
                     ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
   if (full)
-    hipLaunchKernelGGL(se_kmatvec_gram_kernel<SPEC_KK>, grid, dim3(GrShape::THREADS), 0, st, A, rows, B, cols, d, h,
-                       v, partial, chunk_cols, same);
+    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_KK, false>), grid, dim3(GrShape::THREADS), 0, st, A, rows, B,
+                       cols, d, h, v, partial, nullptr, chunk_cols, same);
   else
-    hipLaunchKernelGGL(se_kmatvec_gram_kernel<SPEC_GUARDED>, grid, dim3(GrShape::THREADS), 0, st, A, rows, B, cols, d,
-                       h, v, partial, chunk_cols, same);
+    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_GUARDED, false>), grid, dim3(GrShape::THREADS), 0, st, A, rows,
+                       B, cols, d, h, v, partial, nullptr, chunk_cols, same);
+  return hipGetLastError();
+}
+
+hipError_t launch_se_kmatvec_gram_sym(const double* Z, int64_t n, int64_t d, HyperArg h, const double* v,
+                                      double* partial, double* colpart, int64_t chunk_cols, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (n > 0x7fffff00 || d > 0x7fffffff || chunk_cols % GEMM_BN != 0) return hipErrorInvalidValue;
+  const int64_t nch = (n + chunk_cols - 1) / chunk_cols;
+  dim3 grid((unsigned)((n + GEMM_BM - 1) / GEMM_BM), (unsigned)nch);
+  const bool full = n % GEMM_BM == 0 && d % Chunk<double>::BK == 0 && ((uintptr_t)Z & 15) == 0;
+  if (full)
+    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_KK, true>), grid, dim3(GrShape::THREADS), 0, st, Z, n, Z, n, d,
+                       h, v, partial, colpart, chunk_cols, 1);
+  else
+    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_GUARDED, true>), grid, dim3(GrShape::THREADS), 0, st, Z, n, Z, n,
+                       d, h, v, partial, colpart, chunk_cols, 1);
   return hipGetLastError();
 }
 

@@ -120,6 +120,11 @@ hipError_t launch_kmatvec_partial(const double* A, int64_t rows, const double* B
 // cores (gram.hip); chunk_cols a multiple of 128
 hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
                                   HyperArg h, const double* v, double* partial, int64_t chunk_cols, hipStream_t st);
+// The refinement's K v for the squared exponential with the symmetry of K: Z (n x d) against
+// itself, the blocks at or left of the diagonal only; partial[chunk][i] (chunk_cols % 128
+// == 0) and colpart[ceil(n / 128)][n] (the column sums of the blocks left of the diagonal)
+hipError_t launch_se_kmatvec_gram_sym(const double* Z, int64_t n, int64_t d, HyperArg h, const double* v,
+                                      double* partial, double* colpart, int64_t chunk_cols, hipStream_t st);
 
 // blas2.hip
 // y[r] = beta*yin[r] + alpha * sum_c A[r*lda + c] x[c]   for r < rows (A float64 or float32)
@@ -145,6 +150,10 @@ hipError_t launch_nlml(const double* Ddiag, int64_t b, int64_t n, const double* 
 // r = y - (Kf alpha + s2 alpha) from partial K_f alpha sums
 hipError_t launch_residual_finish(const double* partial, int64_t nch, int64_t n, HyperArg h,
                                   const double* y, const double* alpha, double* r, hipStream_t st);
+// r = y - (K alpha + sigma^2 alpha) from the symmetric products: partial[chunk][i] as above
+// plus colpart[x][i] for x > i / 128 (launch_se_kmatvec_gram_sym)
+hipError_t launch_residual_finish_sym(const double* partial, int64_t nch, const double* colpart, int64_t n, HyperArg h,
+                                      const double* y, const double* alpha, double* r, hipStream_t st);
 // grad[k] = trainable[k] ? 1/2 * (s_l, s_nu, s2 * s_s)[k] : 0, from per-workgroup partials;
 // npadded padded rows each added exactly nu to s_nu and 1 to s_s, which are taken off
 hipError_t launch_grad_finish(const double* partial, int64_t nwg, HyperArg h, int64_t npadded, int t0, int t1,
