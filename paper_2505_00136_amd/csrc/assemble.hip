@@ -57,14 +57,6 @@ GPR_DEV void sqdist_block(const double* __restrict__ A, int64_t rows, int64_t ra
   }
 }
 
-// Tile pair (ti, tj), ti >= tj, of the row-major packed lower triangle y = ti (ti+1)/2 + tj.
-GPR_DEV void pair_of(int64_t y, int64_t& ti, int64_t& tj) {
-  ti = (int64_t)((sqrt(8.0 * (double)y + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= y) ++ti;
-  while (ti * (ti + 1) / 2 > y) --ti;
-  tj = y - ti * (ti + 1) / 2;
-}
-
 // One-dimensional grid over (tile pair, 64 x 64 block of the tile), pair-major.
 __global__ __launch_bounds__(256)
 void assemble_tiles_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, TileLayout L, void* K) {
@@ -213,6 +205,8 @@ hipError_t launch_assemble_tiles(const double* Z, int64_t d, HyperArg h, const T
                                  hipStream_t st) {
   if (L.T == 0) return hipSuccess;
   if (L.n <= (L.T - 1) * L.b || L.n > L.npad()) return hipErrorInvalidValue;
+  // the squared exponential forms its distances on the matrix cores (gram.hip)
+  if (h.kernel == KERNEL_SE) return launch_se_tiles_gram(Z, d, h, L, K, nullptr, st);
   const int64_t nbt = (L.b + KB - 1) / KB;
   const int64_t blocks = nbt * nbt * (L.T * (L.T + 1) / 2);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
@@ -227,6 +221,10 @@ hipError_t launch_halfdist_tiles(const double* Z, int64_t n, int64_t d, HyperArg
   const int64_t blocks = nbt * nbt * (T * (T + 1) / 2);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (n <= (T - 1) * b || n > T * b) return hipErrorInvalidValue;
+  if (h.kernel == KERNEL_SE) {
+    TileLayout L{n, b, T, 8};
+    return launch_se_tiles_gram(Z, d, h, L, nullptr, U, st);
+  }
   hipLaunchKernelGGL(halfdist_tiles_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Z, n, d, h, b, U);
   return hipGetLastError();
 }

@@ -90,6 +90,14 @@ GPR_DEV void resolve_hyper(const HyperArg& h, double& ell, double& nu, double& s
 // identity block: rows and columns n..Tb-1 are zero except for ones on the diagonal, so
 // the factor is L of the n x n matrix bordered by that identity, its log-determinant is
 // unchanged, and solves with zero-padded right-hand sides return zero padding.
+// Tile pair (ti, tj), ti >= tj, of the row-major packed lower triangle y = ti (ti+1)/2 + tj.
+GPR_DEV void pair_of(int64_t y, int64_t& ti, int64_t& tj) {
+  ti = (int64_t)((sqrt(8.0 * (double)y + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= y) ++ti;
+  while (ti * (ti + 1) / 2 > y) --ti;
+  tj = y - ti * (ti + 1) / 2;
+}
+
 struct TileLayout {
   int64_t n, b, T;   // n: number of points (rows of Z), not necessarily T b
   int esize;  // bytes per element in region O (8 or 4)

@@ -11,7 +11,7 @@
 // of every kernel value at a few ulp of nu whatever the offset of the points from the
 // origin; standardised features with l^2 near D (ratio about 1) take the Gram form.  The Matern forms, whose value depends on sqrt(r^2), keep the explicit
 // differences of assemble.hip.  A pair of the same point (the training residual) gets
-// r^2 = 0 exactly.
+// r^2 = 0 exactly; a NaN feature makes every r^2 of its point NaN, as explicit differences do.
 #include "common.h"
 #include "gemm_device.h"
 #include "kernels.h"
@@ -167,7 +167,7 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
           for (int r = 0; r < 4; ++r) {
             const double r2 = na[wm + i * 16 + MfmaOp<double>::row(lane, r)] + nb[wn + j * 16 + (lane & 15)] -
                               2.0 * acc[i][j][r];
-            acc[i][j][r] = r2 > 0.0 ? r2 : 0.0;
+            acc[i][j][r] = r2 < 0.0 ? 0.0 : r2;   // (a NaN stays NaN)
           }
     } else {
       explicit_r2<GrShape::NJ>(A, rows, r0, B, cend, c0, d, smem, acc, lane, wm, wn);
@@ -192,7 +192,7 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
           const int lc = wn + j * 16 + (lane & 15);
           const int64_t col = c0 + lc;
           double r2 = acc[i][j][r];
-          if (same && row == col) r2 = 0.0;
+          if (same && row == col && r2 == r2) r2 = 0.0;   // a point with a NaN feature stays NaN
           if (row < rows && col < cend) {
             const double kv = nu * exp(g * r2);
             s = fma(kv, vj[j], s);
@@ -229,6 +229,125 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
     const int64_t r = r0 + tid;
     if (r < rows) partial[(int64_t)blockIdx.y * rows + r] = s;
   }
+}
+
+// The tiled covariance (OUT = 0, Eq. 2 with the identity padding of the tiled layout) or the
+// gradient's u = r^2 / (2 l^2) tiles (OUT = 1) for the squared exponential, from the Gram
+// products: workgroup x takes the 128 x 128 block x % nbt^2 of tile pair x / nbt^2 (row-
+// major packed lower triangle of tile pairs).  Rows of a tile past its real points read
+// zero features (their kernel values are replaced by the padding; their u, finite, gets
+// zero weight in the gradient).  The Gram form's accuracy rule is the one of the products
+// above: blocks with (max|a|^2 + max|b|^2) / (2 l^2) above kGramRatioMax take explicit
+// differences.
+template <int SPEC, int OUT>
+__global__ __launch_bounds__(GrShape::THREADS, 2)
+void se_tiles_gram_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, TileLayout L, void* K,
+                          double* __restrict__ U) {
+  __shared__ __align__(16) char smem[Chunk<double>::SMEM];
+  __shared__ double na[GEMM_BM], nb[GEMM_BN];
+  __shared__ double maxna, maxnb;
+  __shared__ GemmSeg seg;
+  LdsBuf<double> As = reinterpret_cast<LdsBuf<double>>(smem);
+  LdsBuf<double> Bs = As + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = GrShape::m0(wave), wn = GrShape::n0(wave);
+  const int64_t b = L.b, nbt = (b + GEMM_BM - 1) / GEMM_BM;
+  const int64_t y = (int64_t)blockIdx.x / (nbt * nbt), blk = (int64_t)blockIdx.x % (nbt * nbt);
+  int64_t ti, tj;
+  pair_of(y, ti, tj);
+  const int64_t r0 = (blk / nbt) * GEMM_BM, c0 = (blk % nbt) * GEMM_BN;   // within the tile
+  const int64_t ri = L.rows_of(ti), rj = L.rows_of(tj);                   // real rows of the two tiles
+  const double* A = Z + ti * b * d;
+  const double* B = Z + tj * b * d;
+  double ell, nu, s2;
+  resolve_hyper(h, ell, nu, s2);
+  const double g = -0.5 / (ell * ell);
+  if (tid == 0) seg = GemmSeg{A, B, d, d, 0, 0, (int32_t)d, MODE_KC, MODE_KC, 0, 0};
+  GemmJob job{};
+  job.M = (int32_t)ri;
+  job.N = (int32_t)rj;
+  job.seg0 = 0;
+  job.nseg = 1;
+  row_norms(A, ri, r0, d, na);
+  row_norms(B, rj, c0, d, nb);
+  __syncthreads();
+  max_norm(na, &maxna);
+  __syncthreads();
+  max_norm(nb, &maxnb);
+  __syncthreads();
+  v4d acc[4][GrShape::NJ];
+  if ((maxna + maxnb) * (-g) <= kGramRatioMax) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < GrShape::NJ; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+    gemm_mainloop<double, double, SPEC, GR_WN>(job, &seg, (int)r0, (int)c0, acc, As, Bs);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < GrShape::NJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double r2 = na[wm + i * 16 + MfmaOp<double>::row(lane, r)] + nb[wn + j * 16 + (lane & 15)] -
+                            2.0 * acc[i][j][r];
+          acc[i][j][r] = r2 < 0.0 ? 0.0 : r2;   // (a NaN stays NaN)
+        }
+  } else {
+    explicit_r2<GrShape::NJ>(A, ri, r0, B, rj, c0, d, smem, acc, lane, wm, wn);
+  }
+  const bool diag = ti == tj;
+  double* Dt = (OUT == 0 && diag) ? L.diag(K, ti) : nullptr;
+  void* Ot = (OUT == 0 && !diag) ? L.off(K, ti, tj) : nullptr;
+  double* Ut = OUT == 1 ? U + y * b * b : nullptr;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + wm + i * 16 + MfmaOp<double>::row(lane, r);
+      if (row >= b) continue;
+#pragma unroll
+      for (int j = 0; j < GrShape::NJ; ++j) {
+        const int64_t col = c0 + wn + j * 16 + (lane & 15);
+        if (col >= b) continue;
+        double r2 = acc[i][j][r];
+        if (diag && row == col && r2 == r2) r2 = 0.0;   // a point with a NaN feature stays NaN
+        if (OUT == 1) {
+          Ut[row * b + col] = -g * r2;
+        } else {
+          double v = nu * exp(g * r2);
+          if (row >= ri || col >= rj) v = 0.0;   // padding: identity block, zero border
+          if (diag) {
+            if (row == col) v = row < ri ? v + s2 : 1.0;
+            Dt[row * b + col] = v;
+          } else if (L.esize == 8) {
+            ((double*)Ot)[row * b + col] = v;
+          } else {
+            ((float*)Ot)[row * b + col] = (float)v;
+          }
+        }
+      }
+    }
+}
+
+hipError_t launch_se_tiles_gram(const double* Z, int64_t d, HyperArg h, const TileLayout& L, void* K, double* U,
+                                hipStream_t st) {
+  if (L.T == 0) return hipSuccess;
+  if ((K == nullptr) == (U == nullptr) || d > 0x7fffffff || L.b > 0x7fffff00) return hipErrorInvalidValue;
+  const int64_t nbt = (L.b + GEMM_BM - 1) / GEMM_BM;
+  const int64_t blocks = nbt * nbt * (L.T * (L.T + 1) / 2);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  // the straight-line main loop: whole 128-point blocks in every tile (no padding), whole
+  // 16-deep chunks, 16-byte aligned rows
+  const bool full = L.b % GEMM_BM == 0 && L.n == L.npad() && d % Chunk<double>::BK == 0 && ((uintptr_t)Z & 15) == 0;
+  const dim3 grid((unsigned)blocks), blk(GrShape::THREADS);
+  if (U) {
+    if (full) hipLaunchKernelGGL((se_tiles_gram_kernel<SPEC_KK, 1>), grid, blk, 0, st, Z, d, h, L, K, U);
+    else hipLaunchKernelGGL((se_tiles_gram_kernel<SPEC_GUARDED, 1>), grid, blk, 0, st, Z, d, h, L, K, U);
+  } else {
+    if (full) hipLaunchKernelGGL((se_tiles_gram_kernel<SPEC_KK, 0>), grid, blk, 0, st, Z, d, h, L, K, U);
+    else hipLaunchKernelGGL((se_tiles_gram_kernel<SPEC_GUARDED, 0>), grid, blk, 0, st, Z, d, h, L, K, U);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,

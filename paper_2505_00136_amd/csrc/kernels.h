@@ -120,6 +120,11 @@ hipError_t launch_kmatvec_partial(const double* A, int64_t rows, const double* B
 // cores (gram.hip); chunk_cols a multiple of 128
 hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B, int64_t cols, int64_t d,
                                   HyperArg h, const double* v, double* partial, int64_t chunk_cols, hipStream_t st);
+// The tiled covariance (K != null; layout L, as launch_assemble_tiles) or the gradient's
+// u = r^2 / (2 l^2) tiles of every lower tile pair (U != null; L.esize ignored), squared
+// exponential, distances from Gram products on the matrix cores (gram.hip)
+hipError_t launch_se_tiles_gram(const double* Z, int64_t d, HyperArg h, const TileLayout& L, void* K, double* U,
+                                hipStream_t st);
 // The refinement's K v for the squared exponential with the symmetry of K: Z (n x d) against
 // itself, the blocks at or left of the diagonal only; partial[chunk][i] (chunk_cols % 128
 // == 0) and colpart[ceil(n / 128)][n] (the column sums of the blocks left of the diagonal)
