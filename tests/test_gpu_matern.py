@@ -81,6 +81,36 @@ def test_matern_float32_path_with_refinement(lib):
     assert np.max(np.abs(var - oracle.predict_var(Z, Zs, h, L))) < 1e-4
 
 
+@pytest.mark.parametrize("kernel", ["matern12", "matern32", "matern52"])
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+def test_matern_split_modes_gradient_and_variance(lib, kernel, prec):
+    """Tiles of 256 and 256 test points: the split modes run the inversion, the trace
+    products (whose Matern weights walk the accumulators through LDS) and the variance's
+    substitution from bfloat16 planes.  Bounds as for the squared exponential: mean and
+    NLML 1e-6 after the default sweeps; variance 1e-4 (bf16x3 1e-3); gradient 1e-3
+    (bf16x3 1e-2), normwise."""
+    rng = np.random.default_rng(91)
+    n, tile, D, m = 1024, 256, 6, 256
+    Z = rng.normal(size=(n, D))
+    y = np.sin(Z[:, 0]) + 0.1 * rng.normal(size=n)
+    Zs = rng.normal(size=(m, D))
+    h = Hyper(1.5, 1.0, 0.02, kernel)
+    L, a, f = oracle.fit(Z, y, h)
+    g = _gpu_fit(lib, Z, y, h, tile, prec=prec, sweeps=6 if prec == "bf16x3" else 3, m=m)
+    assert abs(g["nlml"] - f) / abs(f) < 1e-6
+    mean, var = _gpu_predict(lib, g, Zs, h)
+    assert_close(mean, oracle.predict_mean(Z, Zs, h, a), 1e-6)
+    v_tol, g_tol = (1e-3, 1e-2) if prec == "bf16x3" else (1e-4, 1e-3)
+    assert np.max(np.abs(var - oracle.predict_var(Z, Zs, h, L))) < v_tol
+    grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    lib.gpr_nlml_grad(g["Z"], n, D, h, g["K"], tile, prec, g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
+    go = oracle.nlml_grad(Z, h, L, a)
+    ge = grad.cpu().numpy()
+    err = np.linalg.norm(ge - go) / np.linalg.norm(go)
+    print(f"[matern-split] {kernel} {prec}: gradient {err:.2e}", flush=True)
+    assert err < g_tol
+
+
 def test_gp_front_end_with_a_matern_kernel(lib):
     from paper_2505_00136_amd.gp import GP
     ds = datagen.make_dataset(datagen.MSDConfig(n_train=256, n_test=16, D=4, seed=8))
