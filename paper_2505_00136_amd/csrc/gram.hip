@@ -240,7 +240,7 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
 // above: blocks with (max|a|^2 + max|b|^2) / (2 l^2) above kGramRatioMax take explicit
 // differences.
 template <int SPEC, int OUT>
-__global__ __launch_bounds__(GrShape::THREADS, 2)
+__global__ __launch_bounds__(GrShape::THREADS, 4)   // two workgroups per CU: one's epilogue beside the other's products
 void se_tiles_gram_kernel(const double* __restrict__ Z, int64_t d, HyperArg h, TileLayout L, void* K,
                           double* __restrict__ U) {
   __shared__ __align__(16) char smem[Chunk<double>::SMEM];
