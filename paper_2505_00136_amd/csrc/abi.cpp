@@ -763,7 +763,9 @@ SolveWs carve_solve(Carve& c, const TileLayout& L) {
   w.z = c.take<double>(npad);
   w.t = c.take<double>(b);
   w.partial = c.take<double>(solve_partial_rows(L) * b);
-  w.kpart = c.take<double>((size_t)ceil_div(std::max<int64_t>(n, 1), kColsPerChunk) * n);
+  // partial sums of the residual's K alpha: per chunk of kColsPerChunk points (Matern), or
+  // per 128-point block column (kpart) and block row (kcol) of the symmetric products
+  w.kpart = c.take<double>((size_t)ceil_div(std::max<int64_t>(n, 1), std::min<int64_t>(kColsPerChunk, GEMM_BM)) * n);
   w.kcol = c.take<double>((size_t)ceil_div(std::max<int64_t>(n, 1), GEMM_BM) * n);
   w.res = c.take<double>(n);
   w.dvec = c.take<double>(n);
@@ -817,8 +819,8 @@ int solve_impl(const TileLayout& L, const void* K, const double* Z, int64_t d, H
     // r = y - K alpha in float64, K regenerated from Z (matrix-free)
     if (h.kernel == KERNEL_SE) {
       // the symmetry of K halves the pairs
-      HIPCHK(launch_se_kmatvec_gram_sym(Z, n, d, h, alpha, w.kpart, w.kcol, kColsPerChunk, st));
-      HIPCHK(launch_residual_finish_sym(w.kpart, ceil_div(n, kColsPerChunk), w.kcol, n, h, y, alpha, w.res, st));
+      HIPCHK(launch_se_kmatvec_gram_sym(Z, n, d, h, alpha, w.kpart, w.kcol, st));
+      HIPCHK(launch_residual_finish_sym(w.kpart, w.kcol, n, h, y, alpha, w.res, st));
     } else {
       HIPCHK(launch_kmatvec_partial(Z, n, Z, n, d, h, alpha, w.kpart, kColsPerChunk, st));
       HIPCHK(launch_residual_finish(w.kpart, ceil_div(n, kColsPerChunk), n, h, y, alpha, w.res, st));

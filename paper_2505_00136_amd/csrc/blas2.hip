@@ -129,19 +129,20 @@ __global__ void residual_finish_kernel(const double* __restrict__ partial, int64
   r[i] = y[i] - (s + s2 * alpha[i]);
 }
 
-// The same for the symmetric products (launch_se_kmatvec_gram_sym): row i also takes the
-// column sums colpart[x][i] of the blocks x > i / 128 below its own, in order.
-__global__ void residual_finish_sym_kernel(const double* __restrict__ partial, int64_t nch,
-                                           const double* __restrict__ colpart, int64_t n, HyperArg h,
-                                           const double* __restrict__ y, const double* __restrict__ alpha, double* r) {
+// The same for the symmetric products (launch_se_kmatvec_gram_sym): row i takes the row sums
+// rowpart[bj][i] of the block columns bj <= i / 128, then the column sums colpart[x][i] of
+// the blocks x > i / 128 below its own, in order.
+__global__ void residual_finish_sym_kernel(const double* __restrict__ rowpart, const double* __restrict__ colpart,
+                                           int64_t n, HyperArg h, const double* __restrict__ y,
+                                           const double* __restrict__ alpha, double* r) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
+  const int64_t nb = (n + 127) / 128, bi = i / 128;
   double s = 0.0;
-  for (int64_t ch = 0; ch < nch; ++ch) s += partial[ch * n + i];
-  const int64_t nb = (n + 127) / 128;
-  for (int64_t x = i / 128 + 1; x < nb; ++x) s += colpart[x * n + i];
+  for (int64_t bj = 0; bj <= bi; ++bj) s += rowpart[bj * n + i];
+  for (int64_t x = bi + 1; x < nb; ++x) s += colpart[x * n + i];
   r[i] = y[i] - (s + s2 * alpha[i]);
 }
 
@@ -217,11 +218,11 @@ hipError_t launch_residual_finish(const double* partial, int64_t nch, int64_t n,
   return hipGetLastError();
 }
 
-hipError_t launch_residual_finish_sym(const double* partial, int64_t nch, const double* colpart, int64_t n, HyperArg h,
+hipError_t launch_residual_finish_sym(const double* rowpart, const double* colpart, int64_t n, HyperArg h,
                                       const double* y, const double* alpha, double* r, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(residual_finish_sym_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, partial, nch, colpart, n,
-                     h, y, alpha, r);
+  hipLaunchKernelGGL(residual_finish_sym_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, rowpart, colpart, n, h,
+                     y, alpha, r);
   return hipGetLastError();
 }
 

@@ -108,20 +108,14 @@ GPR_DEV void explicit_r2(const double* __restrict__ A, int64_t rlim, int64_t r0,
 // Grid (ceil(rows / 128), chunks); workgroup (x, y) takes rows 128 x .. and the points of
 // chunk y in blocks of 128.  `same`: A and B are the same points (a pair (i, i) is at
 // distance 0).
-// SYM (A = B, the refinement's K alpha): K is symmetric, so workgroup (x, y) takes only the
-// blocks of chunk y at or left of the diagonal block x; a block left of it (c0 < r0) also
-// adds its column sums sum_i k(a_i, b_j) v_i, written to colpart[x][j] (each entry by one
-// workgroup; entries of columns in or right of block x are not written).  The sum over
-// i of k_ij v_j then takes partial over the chunks plus colpart[x][i] over x > i / 128.
-template <int SPEC, bool SYM>
+template <int SPEC>
 __global__ __launch_bounds__(GrShape::THREADS, 2)
 void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const double* __restrict__ B, int64_t cols,
                             int64_t d, HyperArg h, const double* __restrict__ v, double* __restrict__ partial,
-                            double* __restrict__ colpart, int64_t chunk_cols, int same) {
+                            int64_t chunk_cols, int same) {
   __shared__ __align__(16) char smem[Chunk<double>::SMEM];
   __shared__ double na[GEMM_BM], nb[GEMM_BN];
   __shared__ double red[GR_WN][GEMM_BM];
-  __shared__ double va[SYM ? GEMM_BM : 1], cred[SYM ? 2 : 1][SYM ? GEMM_BN : 1];
   __shared__ double maxna, maxnb;
   __shared__ GemmSeg seg;
   LdsBuf<double> As = reinterpret_cast<LdsBuf<double>>(smem);
@@ -130,14 +124,12 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
   const int wm = GrShape::m0(wave), wn = GrShape::n0(wave);
   const int64_t r0 = (int64_t)blockIdx.x * GEMM_BM;
   const int64_t cbeg = (int64_t)blockIdx.y * chunk_cols;
-  int64_t cend = cbeg + chunk_cols < cols ? cbeg + chunk_cols : cols;
-  if (SYM && cend > r0 + GEMM_BN) cend = r0 + GEMM_BN;   // blocks at or left of the diagonal block
+  const int64_t cend = cbeg + chunk_cols < cols ? cbeg + chunk_cols : cols;
   double ell, nu, s2;
   resolve_hyper(h, ell, nu, s2);
   const double g = -0.5 / (ell * ell);
   if (tid == 0) seg = GemmSeg{A, B, d, d, 0, 0, (int32_t)d, MODE_KC, MODE_KC, 0, 0};
   if (tid < GR_WN * GEMM_BM) red[tid / GEMM_BM][tid % GEMM_BM] = 0.0;
-  if (SYM && tid < GEMM_BM) va[tid] = r0 + tid < rows ? v[r0 + tid] : 0.0;
   GemmJob job{};
   job.M = (int32_t)rows;
   job.N = (int32_t)cols;
@@ -172,13 +164,11 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
     } else {
       explicit_r2<GrShape::NJ>(A, rows, r0, B, cend, c0, d, smem, acc, lane, wm, wn);
     }
-    double vj[GrShape::NJ], cs[GrShape::NJ];
-    const bool colsums = SYM && c0 < r0;   // a block left of the diagonal block
+    double vj[GrShape::NJ];
 #pragma unroll
     for (int j = 0; j < GrShape::NJ; ++j) {
       const int64_t col = c0 + wn + j * 16 + (lane & 15);
       vj[j] = col < cend ? v[col] : 0.0;
-      cs[j] = 0.0;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -193,11 +183,7 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
           const int64_t col = c0 + lc;
           double r2 = acc[i][j][r];
           if (same && row == col && r2 == r2) r2 = 0.0;   // a point with a NaN feature stays NaN
-          if (row < rows && col < cend) {
-            const double kv = nu * exp(g * r2);
-            s = fma(kv, vj[j], s);
-            if (colsums) cs[j] = fma(kv, va[lr], cs[j]);
-          }
+          if (row < rows && col < cend) s = fma(nu * exp(g * r2), vj[j], s);
         }
         // the 16 lanes holding this row (different columns), then one lane per row adds
         // the block's sum to its wave's slot
@@ -207,20 +193,7 @@ void se_kmatvec_gram_kernel(const double* __restrict__ A, int64_t rows, const do
         s += __shfl_xor(s, 8);
         if ((lane & 15) == 0) red[wave % GR_WN][lr] += s;
       }
-    if (colsums) {
-      // the four lanes holding each column (rows 16 apart), then the two waves of each
-      // column range (rows 0-63 and 64-127) through LDS, in a fixed order
-#pragma unroll
-      for (int j = 0; j < GrShape::NJ; ++j) {
-        cs[j] += __shfl_xor(cs[j], 16);
-        cs[j] += __shfl_xor(cs[j], 32);
-        if (lane < 16) cred[wave / GR_WN][wn + j * 16 + lane] = cs[j];
-      }
-      __syncthreads();
-      if (tid < GEMM_BN && c0 + tid < cend)
-        colpart[(int64_t)blockIdx.x * cols + c0 + tid] = cred[0][tid] + cred[1][tid];
-    }
-    __syncthreads();   // nb, cred and the LDS operand buffers are rewritten by the next block
+    __syncthreads();   // nb and the LDS operand buffers are rewritten by the next block
   }
   if (tid < GEMM_BM) {
     double s = 0.0;
@@ -363,27 +336,145 @@ hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B
   const bool full = rows % GEMM_BM == 0 && cols % GEMM_BN == 0 && d % Chunk<double>::BK == 0 &&
                     ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
   if (full)
-    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_KK, false>), grid, dim3(GrShape::THREADS), 0, st, A, rows, B,
-                       cols, d, h, v, partial, nullptr, chunk_cols, same);
+    hipLaunchKernelGGL(se_kmatvec_gram_kernel<SPEC_KK>, grid, dim3(GrShape::THREADS), 0, st, A, rows, B, cols, d, h,
+                       v, partial, chunk_cols, same);
   else
-    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_GUARDED, false>), grid, dim3(GrShape::THREADS), 0, st, A, rows,
-                       B, cols, d, h, v, partial, nullptr, chunk_cols, same);
+    hipLaunchKernelGGL(se_kmatvec_gram_kernel<SPEC_GUARDED>, grid, dim3(GrShape::THREADS), 0, st, A, rows, B, cols, d,
+                       h, v, partial, chunk_cols, same);
   return hipGetLastError();
 }
 
+// The refinement's K v with the symmetry of K (A = B = Z): one 128 x 128 block of the
+// lower triangle per workgroup (block pair y = bi (bi+1)/2 + bj, bj <= bi), two workgroups
+// per CU.  Its row sums sum_j k_ij v_j go to rowpart[bj][i] for its rows i and, below the
+// diagonal, its column sums sum_i k_ij v_i to colpart[bi][j] for its columns j; each entry
+// is written by one workgroup, and row i of K v is the sum of rowpart[bj][i] over
+// bj <= i / 128 and colpart[x][i] over x > i / 128 (launch_residual_finish_sym).
+template <int SPEC>
+__global__ __launch_bounds__(GrShape::THREADS, 4)
+void se_kmatvec_sym_kernel(const double* __restrict__ Z, int64_t n, int64_t d, HyperArg h,
+                           const double* __restrict__ v, double* __restrict__ rowpart, double* __restrict__ colpart) {
+  __shared__ __align__(16) char smem[Chunk<double>::SMEM];
+  __shared__ double na[GEMM_BM], nb[GEMM_BN], va[GEMM_BM], vb[GEMM_BN];
+  __shared__ double red[GR_WN][GEMM_BM], cred[2][GEMM_BN];
+  __shared__ double maxna, maxnb;
+  __shared__ GemmSeg seg;
+  LdsBuf<double> As = reinterpret_cast<LdsBuf<double>>(smem);
+  LdsBuf<double> Bs = As + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = GrShape::m0(wave), wn = GrShape::n0(wave);
+  int64_t bi, bj;
+  pair_of((int64_t)blockIdx.x, bi, bj);
+  const int64_t r0 = bi * GEMM_BM, c0 = bj * GEMM_BN;
+  const bool diag = bi == bj;
+  double ell, nu, s2;
+  resolve_hyper(h, ell, nu, s2);
+  const double g = -0.5 / (ell * ell);
+  if (tid == 0) seg = GemmSeg{Z, Z, d, d, 0, 0, (int32_t)d, MODE_KC, MODE_KC, 0, 0};
+  if (tid < GEMM_BM) va[tid] = r0 + tid < n ? v[r0 + tid] : 0.0;
+  if (tid >= GEMM_BM && tid < GEMM_BM + GEMM_BN) {
+    const int t = tid - GEMM_BM;
+    vb[t] = c0 + t < n ? v[c0 + t] : 0.0;
+  }
+  GemmJob job{};
+  job.M = (int32_t)n;
+  job.N = (int32_t)n;
+  job.seg0 = 0;
+  job.nseg = 1;
+  row_norms(Z, n, r0, d, na);
+  row_norms(Z, n, c0, d, nb);
+  __syncthreads();
+  max_norm(na, &maxna);
+  __syncthreads();
+  max_norm(nb, &maxnb);
+  __syncthreads();
+  v4d acc[4][GrShape::NJ];
+  if ((maxna + maxnb) * (-g) <= kGramRatioMax) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < GrShape::NJ; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+    gemm_mainloop<double, double, SPEC, GR_WN>(job, &seg, (int)r0, (int)c0, acc, As, Bs);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < GrShape::NJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double r2 = na[wm + i * 16 + MfmaOp<double>::row(lane, r)] + nb[wn + j * 16 + (lane & 15)] -
+                            2.0 * acc[i][j][r];
+          acc[i][j][r] = r2 < 0.0 ? 0.0 : r2;   // (a NaN stays NaN)
+        }
+  } else {
+    explicit_r2<GrShape::NJ>(Z, n, r0, Z, n, c0, d, smem, acc, lane, wm, wn);
+  }
+  double cs[GrShape::NJ];
+#pragma unroll
+  for (int j = 0; j < GrShape::NJ; ++j) cs[j] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lr = wm + i * 16 + MfmaOp<double>::row(lane, r);
+      const int64_t row = r0 + lr;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < GrShape::NJ; ++j) {
+        const int lc = wn + j * 16 + (lane & 15);
+        const int64_t col = c0 + lc;
+        double r2 = acc[i][j][r];
+        if (diag && row == col && r2 == r2) r2 = 0.0;   // a point with a NaN feature stays NaN
+        if (row < n && col < n) {
+          const double kv = nu * exp(g * r2);
+          s = fma(kv, vb[lc], s);
+          if (!diag) cs[j] = fma(kv, va[lr], cs[j]);
+        }
+      }
+      // the 16 lanes holding this row (different columns); one lane per row writes its
+      // wave's sum (the waves of one column range hold different rows)
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 8);
+      if ((lane & 15) == 0) red[wave % GR_WN][lr] = s;
+    }
+  if (!diag) {
+    // the four lanes holding each column (rows 16 apart), then the two waves of each
+    // column range (rows 0-63 and 64-127)
+#pragma unroll
+    for (int j = 0; j < GrShape::NJ; ++j) {
+      cs[j] += __shfl_xor(cs[j], 16);
+      cs[j] += __shfl_xor(cs[j], 32);
+      if (lane < 16) cred[wave / GR_WN][wn + j * 16 + lane] = cs[j];
+    }
+  }
+  __syncthreads();
+  if (tid < GEMM_BM && r0 + tid < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < GR_WN; ++q) t += red[q][tid];
+    rowpart[bj * n + r0 + tid] = t;
+  }
+  if (!diag && tid >= GEMM_BM && tid < GEMM_BM + GEMM_BN && c0 + (tid - GEMM_BM) < n) {
+    const int t = tid - GEMM_BM;
+    colpart[bi * n + c0 + t] = cred[0][t] + cred[1][t];
+  }
+}
+
 hipError_t launch_se_kmatvec_gram_sym(const double* Z, int64_t n, int64_t d, HyperArg h, const double* v,
-                                      double* partial, double* colpart, int64_t chunk_cols, hipStream_t st) {
+                                      double* rowpart, double* colpart, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (n > 0x7fffff00 || d > 0x7fffffff || chunk_cols % GEMM_BN != 0) return hipErrorInvalidValue;
-  const int64_t nch = (n + chunk_cols - 1) / chunk_cols;
-  dim3 grid((unsigned)((n + GEMM_BM - 1) / GEMM_BM), (unsigned)nch);
+  if (n > 0x7fffff00 || d > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t nbk = (n + GEMM_BM - 1) / GEMM_BM;
+  const int64_t blocks = nbk * (nbk + 1) / 2;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const bool full = n % GEMM_BM == 0 && d % Chunk<double>::BK == 0 && ((uintptr_t)Z & 15) == 0;
   if (full)
-    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_KK, true>), grid, dim3(GrShape::THREADS), 0, st, Z, n, Z, n, d,
-                       h, v, partial, colpart, chunk_cols, 1);
+    hipLaunchKernelGGL((se_kmatvec_sym_kernel<SPEC_KK>), dim3((unsigned)blocks), dim3(GrShape::THREADS), 0, st, Z, n,
+                       d, h, v, rowpart, colpart);
   else
-    hipLaunchKernelGGL((se_kmatvec_gram_kernel<SPEC_GUARDED, true>), grid, dim3(GrShape::THREADS), 0, st, Z, n, Z, n,
-                       d, h, v, partial, colpart, chunk_cols, 1);
+    hipLaunchKernelGGL((se_kmatvec_sym_kernel<SPEC_GUARDED>), dim3((unsigned)blocks), dim3(GrShape::THREADS), 0, st,
+                       Z, n, d, h, v, rowpart, colpart);
   return hipGetLastError();
 }
 

@@ -126,10 +126,11 @@ hipError_t launch_se_kmatvec_gram(const double* A, int64_t rows, const double* B
 hipError_t launch_se_tiles_gram(const double* Z, int64_t d, HyperArg h, const TileLayout& L, void* K, double* U,
                                 hipStream_t st);
 // The refinement's K v for the squared exponential with the symmetry of K: Z (n x d) against
-// itself, the blocks at or left of the diagonal only; partial[chunk][i] (chunk_cols % 128
-// == 0) and colpart[ceil(n / 128)][n] (the column sums of the blocks left of the diagonal)
+// itself, one 128 x 128 block of the lower triangle per workgroup; rowpart[ceil(n / 128)][n]
+// (row sums of each block column) and colpart[ceil(n / 128)][n] (column sums of the blocks
+// below the diagonal), combined by launch_residual_finish_sym
 hipError_t launch_se_kmatvec_gram_sym(const double* Z, int64_t n, int64_t d, HyperArg h, const double* v,
-                                      double* partial, double* colpart, int64_t chunk_cols, hipStream_t st);
+                                      double* rowpart, double* colpart, hipStream_t st);
 
 // blas2.hip
 // y[r] = beta*yin[r] + alpha * sum_c A[r*lda + c] x[c]   for r < rows (A float64 or float32)
@@ -155,9 +156,9 @@ hipError_t launch_nlml(const double* Ddiag, int64_t b, int64_t n, const double* 
 // r = y - (Kf alpha + s2 alpha) from partial K_f alpha sums
 hipError_t launch_residual_finish(const double* partial, int64_t nch, int64_t n, HyperArg h,
                                   const double* y, const double* alpha, double* r, hipStream_t st);
-// r = y - (K alpha + sigma^2 alpha) from the symmetric products: partial[chunk][i] as above
-// plus colpart[x][i] for x > i / 128 (launch_se_kmatvec_gram_sym)
-hipError_t launch_residual_finish_sym(const double* partial, int64_t nch, const double* colpart, int64_t n, HyperArg h,
+// r = y - (K alpha + sigma^2 alpha) from the symmetric products (launch_se_kmatvec_gram_sym):
+// row i adds rowpart[bj][i] for bj <= i / 128, then colpart[x][i] for x > i / 128
+hipError_t launch_residual_finish_sym(const double* rowpart, const double* colpart, int64_t n, HyperArg h,
                                       const double* y, const double* alpha, double* r, hipStream_t st);
 // grad[k] = trainable[k] ? 1/2 * (s_l, s_nu, s2 * s_s)[k] : 0, from per-workgroup partials;
 // npadded padded rows each added exactly nu to s_nu and 1 to s_s, which are taken off
