@@ -94,3 +94,27 @@ def test_mixed_gradient_and_full_cov(lib, dense_case):
     grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
     lib.gpr_nlml_grad(g["Z"], g["n"], g["d"], h, g["K"], 200, "fp32", g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
     np.testing.assert_allclose(grad.cpu().numpy(), go, rtol=1e-3, atol=1e-3 * np.max(np.abs(go)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "bf16x3"])
+def test_mixed_optimize_follows_oracle_adam(lib, prec):
+    """gpr_optimize in the mixed modes with tiles of 256 (the split modes' gradients from
+    bfloat16 planes): five Adam steps stay on the oracle's float64 trajectory to the
+    mixed-mode bounds -- NLML trace 1e-6 relative; theta 1e-4 absolute, since each Adam
+    step moves theta by about lr in a direction set by the sign pattern of m / sqrt(v),
+    which gradient errors of 1e-5 relative do not change."""
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=1024, n_test=8, D=8, seed=13))
+    theta0 = [0.0, 0.0, math.log(0.1)]
+    th_o, tr_o = oracle.optimize(ds.Z, ds.y, theta0, steps=5, lr=0.1)
+    n, d, tile = 1024, 8, 256
+    dev = "cuda:0"
+    Zt, yt = torch.tensor(ds.Z, device=dev), torch.tensor(ds.y, device=dev)
+    K = torch.empty(lib.gpr_tiles_bytes(n, tile, prec), dtype=torch.uint8, device=dev)
+    wsb = lib.gpr_workspace_size(n, 0, d, tile, prec)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    th, st, tr = lib.gpr_optimize(Zt, yt, n, d, tile, prec, theta0, (1, 1, 1), 5, 0.1, 0.9, 0.999, 1e-8, None,
+                                  K, ws, wsb)
+    print(f"[mixed-optimize] {prec}: theta {np.max(np.abs(np.array(th) - th_o)):.2e}, "
+          f"trace {np.max(np.abs(np.array(tr) - tr_o) / np.abs(tr_o)):.2e}", flush=True)
+    np.testing.assert_allclose(tr, tr_o, rtol=1e-6)
+    np.testing.assert_allclose(th, th_o, rtol=0, atol=1e-4)
