@@ -157,7 +157,13 @@ GPR_API int gpr_workspace_size(int64_t n, int64_t m, int64_t d, int64_t tile, in
  * vectors; Section 4.2: tile by tile).  Writes regions D and O of K_tiles with
  * K_ij = nu exp(-|z_i - z_j|^2 / (2 l^2)) + sigma^2 [i == j], lower tiles only
  * (diagonal tiles in full), and the identity padding for i or j >= n.  Z: n x d
- * float64 (read only; rows beyond n are never read).  K_tiles: out. */
+ * float64 (read only; rows beyond n are never read).  K_tiles: out.
+ * Accuracy: for the squared exponential the squared distances of a 128 x 128 block of
+ * points come from |z_i|^2 + |z_j|^2 - 2 z_i . z_j on the matrix cores when
+ * (max |z_i|^2 + max |z_j|^2) / (2 l^2) <= 16 over the block, from explicit differences
+ * otherwise (and for the Matern kernels), so every kernel value is within a few dozen
+ * ulp of nu; a point with itself is at distance 0, a NaN feature gives NaN values.  The
+ * kernel-vector products of gpr_solve's residual and of gpr_predict follow the same rule. */
 GPR_API int gpr_assemble(const double* Z, int64_t n, int64_t d, gpr_hyper_t h, int64_t tile, int prec,
                          void* K_tiles, void* stream);
 
