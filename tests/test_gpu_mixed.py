@@ -118,3 +118,24 @@ def test_mixed_optimize_follows_oracle_adam(lib, prec):
           f"trace {np.max(np.abs(np.array(tr) - tr_o) / np.abs(tr_o)):.2e}", flush=True)
     np.testing.assert_allclose(tr, tr_o, rtol=1e-6)
     np.testing.assert_allclose(th, th_o, rtol=0, atol=1e-4)
+
+
+@pytest.mark.parametrize("prec,m", [("bf16x6", 256), ("bf16x3", 300)])
+def test_split_modes_single_tile(lib, prec, m):
+    """One tile of 512 (T = 1): the split modes' inversion has no products, the trace one
+    job with the alpha subtraction, the variance one block; 300 test points (not a
+    multiple of 256) take the float32 substitution beside the split gradient."""
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=512, n_test=m, D=8, seed=17))
+    h = Hyper(math.sqrt(8), 1.0, 0.01)
+    L, a, f = oracle.fit(ds.Z, ds.y, h)
+    g = _gpu_fit(lib, ds.Z, ds.y, h, 512, prec=prec, sweeps=-1, m=m)
+    assert abs(g["nlml"] - f) / abs(f) < 1e-6
+    assert _rel(g["alpha"].cpu().numpy(), a) < 1e-6
+    mean, var = _gpu_predict(lib, g, ds.Zs, h)
+    assert _rel(mean, oracle.predict_mean(ds.Z, ds.Zs, h, a)) < 1e-6
+    v_tol, g_tol = (1e-3, 1e-2) if prec == "bf16x3" else (1e-4, 1e-3)
+    assert _rel(var, oracle.predict_var(ds.Z, ds.Zs, h, L)) < v_tol
+    grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    lib.gpr_nlml_grad(g["Z"], 512, 8, h, g["K"], 512, prec, g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
+    go = oracle.nlml_grad(ds.Z, h, L, a)
+    assert _rel(grad.cpu().numpy(), go) < g_tol
