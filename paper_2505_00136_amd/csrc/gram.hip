@@ -1,5 +1,6 @@
-// Fused kernel-vector products for the squared exponential (Eq. 2) with the squared
-// distances from Gram products on the matrix cores:
+// Squared-exponential kernel values (Eq. 2) with the squared distances from Gram products
+// on the matrix cores -- fused kernel-vector products (posterior mean, Eq. 3, and the
+// refinement residual), the tiled assembly and the gradient's scaled distances:
 //   r_ij^2 = |a_i|^2 + |b_j|^2 - 2 a_i . b_j,
 // the dot products of a 128 x 128 block of point pairs being one tile product with depth D
 // (the tile-GEMM main loop of gemm_device.h, both operands k-contiguous: the rows of the
@@ -9,9 +10,10 @@
 // (max |a|^2 + max |b|^2) / (2 l^2) exceeds kGramRatioMax therefore forms its distances
 // from explicit differences instead (features staged through LDS), which keeps the error
 // of every kernel value at a few ulp of nu whatever the offset of the points from the
-// origin; standardised features with l^2 near D (ratio about 1) take the Gram form.  The Matern forms, whose value depends on sqrt(r^2), keep the explicit
-// differences of assemble.hip.  A pair of the same point (the training residual) gets
-// r^2 = 0 exactly; a NaN feature makes every r^2 of its point NaN, as explicit differences do.
+// origin; standardised features with l^2 near D (ratio about 1) take the Gram form.  The
+// Matern forms, whose value depends on sqrt(r^2), keep the explicit differences of
+// assemble.hip.  A pair of the same point (the training residual) gets r^2 = 0 exactly; a
+// NaN feature makes every r^2 of its point NaN, as explicit differences do.
 #include "common.h"
 #include "gemm_device.h"
 #include "kernels.h"
