@@ -139,3 +139,34 @@ def test_split_modes_single_tile(lib, prec, m):
     lib.gpr_nlml_grad(g["Z"], 512, 8, h, g["K"], 512, prec, g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
     go = oracle.nlml_grad(ds.Z, h, L, a)
     assert _rel(grad.cpu().numpy(), go) < g_tol
+
+
+def test_split_modes_more_tiles_than_one_split_launch(lib):
+    """33 tiles of 256 (n = 8448): the plane splits of a block row (up to 33 tiles) take
+    two launches of at most 32 tiles each.  Against the float64 path of the same library
+    (pinned to the oracle by the parity tests; the oracle itself would take a minute at
+    this size) at the bf16x6 bounds: NLML and mean 1e-6, gradient 1e-3; the variance
+    within 1e-5 nu absolute -- with 8 features the posterior variances here are small
+    (down to 2.6e-4 nu), so relative errors are large for every mixed mode (float32
+    products: 2.7e-3 relative, 8.5e-6 absolute; bf16x6 planes: 2.4e-4, 1.7e-6)."""
+    n, tile, D, m = 8448, 256, 8, 256
+    ds = datagen.make_dataset(datagen.MSDConfig(n_train=n, n_test=m, D=D, seed=23))
+    h = Hyper(math.sqrt(D), 1.0, 0.01)
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x6"):
+        g = _gpu_fit(lib, ds.Z, ds.y, h, tile, prec=prec, sweeps=-1, m=m)
+        mean, var = _gpu_predict(lib, g, ds.Zs, h)
+        grad = torch.empty(3, dtype=torch.float64, device="cuda:0")
+        lib.gpr_nlml_grad(g["Z"], n, D, h, g["K"], tile, prec, g["alpha"], (1, 1, 1), grad, g["ws"], g["wsb"])
+        res[prec] = dict(nlml=g["nlml"], mean=mean, var=var, grad=grad.cpu().numpy())
+    r, f = res["bf16x6"], res["fp64"]
+    err = _rel(r["grad"], f["grad"])
+    for p in ("fp32", "bf16x6"):
+        q = res[p]
+        print(f"[split-33-tiles] {p}: var {_rel(q['var'], f['var']):.2e} (max abs {np.max(np.abs(q['var'] - f['var'])):.2e}, "
+              f"min var {np.min(f['var']):.2e}), grad {_rel(q['grad'], f['grad']):.2e}, "
+              f"mean {_rel(q['mean'], f['mean']):.2e}", flush=True)
+    assert abs(r["nlml"] - f["nlml"]) / abs(f["nlml"]) < 1e-6
+    assert _rel(r["mean"], f["mean"]) < 1e-6
+    assert np.max(np.abs(r["var"] - f["var"])) < 1e-5 * h.signal_var
+    assert err < 1e-3
